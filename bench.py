@@ -1,0 +1,204 @@
+"""Benchmark of one full Barnes-Hut force step on one MI355X.
+
+Default workload: Plummer sphere of N = 2^22 equal-mass particles (seed 3,
+Henon units), theta = 0.75, ncrit 16, groups of <= 64, float32 interactions,
+float64 multipoles.  A step is the whole hot path on inputs already resident
+in HBM: bounding cube, keys, radix sort, reorder, octree + groups, multipoles,
+MAC preparation and the group walk, with results in the caller's order.
+
+Prints ONE JSON line on stdout: particles/s of the full step (whole job),
+interactions/s, per-stage times (HIP events on the library's stream), the
+walk kernel's roofline (float32 vector ALU bound) and the float64 CPU
+oracle's throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+F_PC = 53  # flops per particle-cell interaction (monopole + traceless quadrupole, rsqrt = 1)
+F_PP = 20  # flops per particle-particle interaction (rsqrt = 1)
+PEAK_FP32_TFLOPS = 157.3  # MI355X published float32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # without packed float32 instructions (disabled in this build)
+WALK_SOURCES = ("paper_1204_2280_amd/csrc/walk_kernel.hip", "paper_1204_2280_amd/csrc/mibh_device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_hbm_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def walk_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per walk launch from committed rocprofv3 counter runs, if they
+    were taken on the current walk kernel source and this workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != walk_source_hash() or t.get("workload") != workload:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 16):
+    """The float64 oracle on the host cores: full tree build on all particles
+    plus the walk of a sample of groups, the walk time scaled to all groups."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    T = oracle.Tree(pos, mass)
+    t_build = time.perf_counter() - t0
+    ng = T.ngroups
+    width = max(1, int(ng * frac / n_ranges))
+    starts = np.linspace(0, ng - width, n_ranges).astype(np.int64)
+    t_walk = 0.0
+    sampled = 0
+    for s in starts:
+        t0 = time.perf_counter()
+        T.walk(theta, groups=(int(s), int(s) + width))
+        t_walk += time.perf_counter() - t0
+        sampled += width
+    t_step = t_build + t_walk * ng / sampled
+    n = len(mass)
+    return {
+        "value": n / t_step,
+        "unit": "particles/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"float64 oracle: full tree build of all {n} particles ({t_build:.2f} s, one thread) + "
+                   f"walk of {sampled} of {ng} groups in {n_ranges} ranges ({t_walk:.2f} s), walk time "
+                   f"scaled by {ng / sampled:.1f}; estimated step {t_step:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 22)
+    ap.add_argument("--theta", type=float, default=0.75)
+    ap.add_argument("--precision", choices=("plain", "kahan"), default="plain")
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--walk-waves", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the force step is single-GPU); --gpus {args.gpus} "
+              "is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1204_2280_amd import mibh, workloads
+
+    n, theta = args.n, args.theta
+    workload = f"plummer_n{n}_seed{args.seed}_theta{theta:g}_{args.precision}"
+    log(f"[bench] workload {workload}")
+    pos, _, mass = workloads.plummer(n, args.seed, with_velocities=False)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    p = torch.from_numpy(pos).to(dev)
+    m = torch.from_numpy(mass).to(dev)
+    ctx = mibh.Context(n, device=dev, precision=1 if args.precision == "kahan" else 0,
+                       walk_waves=args.walk_waves)
+    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((n,), dtype=torch.float32, device=dev)
+
+    for _ in range(args.warmup):
+        ctx.forces(p, m, theta, acc, pot)
+    ctx.sync()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+
+    ctx.profile_begin(args.steps)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(ctx.stream)
+    for _ in range(args.steps):
+        ctx.forces(p, m, theta, acc, pot)
+    end.record(ctx.stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    stages = ctx.profile_read()
+    ctx.sync()
+    st = ctx.stats()
+    log(f"[bench] timed {args.steps} steps: {total_ms:.2f} ms")
+
+    ms_step = total_ms / args.steps
+    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in mibh.STAGES}
+    walk_ms = stage_ms["walk"]
+    inter = st["sum_pc"] + st["sum_pp"]
+    flops = F_PC * st["sum_pc"] + F_PP * st["sum_pp"]
+    achieved = flops / (walk_ms * 1e-3) / 1e12
+    paper_sections = {
+        "sorting": stage_ms["sorting"], "moving": stage_ms["moving"],
+        "tree_construction": stage_ms["tree_construction"],
+        "multipoles": stage_ms["multipoles"] + stage_ms["mac_prep"], "tree_traverse": walk_ms,
+    }
+    traffic = measured_traffic(workload)
+
+    result = {
+        "metric": "particles/s per full force step (build+walk), N=2^22 theta=0.75; interactions/s",
+        "value": n * args.steps / (total_ms * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "theta": theta, "ncrit": 16, "group_cap": 64,
+                   "precision": args.precision, "seed": args.seed, "multipoles": "f64",
+                   "interactions": "f32"},
+        "interactions_per_s": inter * args.steps / (total_ms * 1e-3),
+        "interactions_per_particle": {"pc": st["sum_pc"] / n, "pp": st["sum_pp"] / n},
+        "stage_ms": stage_ms,
+        "paper_sections_ms": paper_sections,
+        "walk_share": walk_ms / ms_step,
+        "tree": {"ncells": st["ncells"], "ngroups": st["ngroups"], "nleaves": st["nleaves"],
+                 "depth": st["depth"]},
+        "roofline": {
+            "kernel": "k_walk (group tree walk)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic,
+            "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+            "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+            "flops_per_launch": flops,
+            "walk_ms": walk_ms,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(pos, mass, theta)
+        log("[bench] cpu baseline done")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

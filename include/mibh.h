@@ -1,0 +1,177 @@
+/*
+ * mibh.h - C ABI of an MI355X (gfx950) Barnes-Hut force step.
+ *
+ * The method is the GPU tree-code of Bedorf, Gaburov & Portegies Zwart,
+ * "Bonsai: A GPU Tree-Code" (arXiv:1204.2280): every part of one force
+ * evaluation runs on the GPU with no host<->device traffic (Abstract,
+ * Introduction), in the parts the Results section times separately - sorting
+ * along a Morton curve, moving particle properties, tree construction,
+ * multipole moments and the tree traverse with a Barnes (1994) / vector-
+ * machine (Barnes 1990) opening criterion theta.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers on the context's device; the
+ *     caller owns them.  Host pointers are named h_* or are plain outputs.
+ *   - Arrays are C-contiguous float32: positions and accelerations are
+ *     [n][3] (x, y, z interleaved), masses and potentials are [n].
+ *   - All work is enqueued on the stream given to mibh_create; calls return
+ *     once enqueued unless they say "synchronises".
+ *   - Every call returns a mibh_status; no exception crosses the ABI.  On an
+ *     error the thread-local message is available from mibh_last_error().
+ *   - Device-side conditions (non-finite input, capacity overflow) are
+ *     recorded in device memory and reported by the next synchronising call
+ *     (mibh_sync, mibh_stats, mibh_energy).
+ *   - The library never allocates device memory: the caller passes one
+ *     workspace of mibh_workspace_bytes() bytes at mibh_create.
+ *   - Calls on one context are not thread-safe; contexts are independent.
+ */
+#ifndef MIBH_H
+#define MIBH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mibh_ctx mibh_ctx;
+
+typedef enum {
+    MIBH_OK = 0,
+    MIBH_EINVAL = -1,      /* bad argument: null pointer, n out of range, theta <= 0, ... */
+    MIBH_ENOMEM = -2,      /* workspace smaller than mibh_workspace_bytes() */
+    MIBH_EHIP = -3,        /* a HIP runtime call failed */
+    MIBH_ESTATE = -4,      /* calls out of order (e.g. forces before build_tree) */
+    MIBH_EOVERFLOW = -5,   /* a device-side capacity was exceeded (results invalid) */
+    MIBH_ENONFINITE = -6   /* a position or mass was NaN/Inf, or a mass was negative */
+} mibh_status;
+
+enum { MIBH_PLAIN = 0, MIBH_KAHAN = 1 };
+
+/* Parameters of the method and of the walk kernel. */
+typedef struct {
+    int32_t ncrit;      /* leaf capacity: a cell splits iff it holds more than ncrit
+                           particles and is above level 20 (default 16) */
+    int32_t group_cap;  /* groups are the largest cells with <= group_cap particles;
+                           1 <= ncrit <= group_cap <= 64 (default 64) */
+    float eps2;         /* Plummer softening length squared (default 0) */
+    float G;            /* gravitational constant (default 1) */
+    int32_t precision;  /* MIBH_PLAIN or MIBH_KAHAN per-particle accumulation (default plain) */
+    int32_t walk_waves; /* waves of the persistent walk launch; 0 = 4096 (16 per CU of a
+                           256-CU MI355X) */
+    int32_t pc_cap;     /* per-wave particle-cell list entries before an evaluation flush
+                           (>= 64; default 8192) */
+    int32_t pp_cap;     /* per-wave particle-particle list entries before a flush
+                           (>= 64; default 4096) */
+} mibh_params;
+
+/* Fills the defaults listed above. */
+void mibh_default_params(mibh_params *p);
+
+/* Bytes of device workspace a context needs for up to n_max particles with
+ * these parameters (NULL = defaults).  Returns 0 if the arguments are invalid
+ * (n_max < 1 or >= 2^31, or invalid parameters). */
+size_t mibh_workspace_bytes(int64_t n_max, const mibh_params *p);
+
+/* Creates a context on the current HIP device.  d_workspace must hold at
+ * least mibh_workspace_bytes(n_max, p) bytes, 256-byte aligned, and stay
+ * valid until mibh_destroy; stream is a hipStream_t (NULL = null stream).
+ * Errors: EINVAL (bad parameters or pointers), ENOMEM (workspace too small),
+ * EHIP. */
+mibh_status mibh_create(const mibh_params *p, int64_t n_max, void *d_workspace,
+                        size_t workspace_bytes, void *stream, mibh_ctx **out);
+
+/* Frees the host-side context (the workspace stays the caller's). */
+mibh_status mibh_destroy(mibh_ctx *ctx);
+
+/* Tree construction: bounding cube, 60-bit Morton keys, stable radix sort,
+ * reorder of positions and masses, breadth-first sparse octree and groups
+ * (the sorting / moving / tree-construction parts of the Results section).
+ * d_pos [n][3] and d_mass [n] must stay valid and unchanged until the next
+ * build_tree; 1 <= n <= n_max.  Errors: EINVAL.  Non-finite inputs are
+ * flagged on the device (ENONFINITE at the next synchronising call). */
+mibh_status mibh_build_tree(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n);
+
+/* Multipole moments of every cell (the "tree-properties"): float64 mass,
+ * centre of mass and second moments, reduced bottom-up level by level, then
+ * the float32 monopole + traceless quadrupole used by the walk.
+ * Errors: ESTATE if no tree was built. */
+mibh_status mibh_compute_multipoles(mibh_ctx *ctx);
+
+/* Tree traverse for all groups with opening parameter theta > 0 (the MAC of
+ * the Results section), particle-cell and particle-particle interactions in
+ * float32, results written in the caller's particle order: d_acc [n][3],
+ * d_pot [n] (potential, negative; self term excluded).
+ * Errors: EINVAL (theta not finite or <= 0, null outputs), ESTATE. */
+mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float *d_pot);
+
+/* build_tree + compute_multipoles + compute_forces in order. */
+mibh_status mibh_forces(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n,
+                        float theta, float *d_acc, float *d_pot);
+
+/* Synchronises: waits for the context's stream and reports device flags
+ * (ENONFINITE, EOVERFLOW) raised since the last build_tree. */
+mibh_status mibh_sync(mibh_ctx *ctx);
+
+/* Per-step statistics; synchronises. */
+typedef struct {
+    int64_t n, ncells, ngroups, nleaves;
+    int32_t depth;         /* deepest cell level */
+    int32_t root_k;        /* root cube side is 2^root_k */
+    uint64_t sum_pc;       /* sum over particles of their group's particle-cell count */
+    uint64_t sum_pp;       /* sum over particles of their group's particle-particle count */
+    uint32_t flags;        /* device flags: 1 non-finite, 2 negative mass, 4 stack, 8 cell capacity */
+} mibh_stats_t;
+mibh_status mibh_stats(mibh_ctx *ctx, mibh_stats_t *out);
+
+/* Total energies in float64 with a fixed-shape (deterministic) reduction:
+ * W = 1/2 sum m phi over the last compute_forces, T = 1/2 sum m |v|^2 for
+ * d_vel [n][3] (NULL: T = 0).  Synchronises.  Errors: ESTATE. */
+mibh_status mibh_energy(mibh_ctx *ctx, const float *d_vel, double *T, double *W);
+
+/* Device-to-device copy of an internal array of the current tree (for tests
+ * and tools).  bytes must be at least the size reported by mibh_export_bytes.
+ *   MIBH_EXPORT_KEYS    uint64 [n]        sorted Morton keys
+ *   MIBH_EXPORT_PERM    uint32 [n]        sorted position -> input index
+ *   MIBH_EXPORT_CELLS   uint32 [ncells][4] first, count, child_first (0 = leaf),
+ *                                         level << 8 | nchild
+ *   MIBH_EXPORT_GROUPS  uint32 [ngroups][2] first, level << 8 | count
+ *   MIBH_EXPORT_COUNTS  uint32 [ngroups][2] particle-cell count, particle-particle count
+ *   MIBH_EXPORT_MULTIPOLES float64 [ncells][10] M, com x y z, S xx yy zz xy xz yz
+ *   MIBH_EXPORT_DELTA   float64 [ncells]  |com - geometric centre|
+ *   MIBH_EXPORT_MAC     float32 [ncells][4] com x y z (float32), r_open^2
+ *   MIBH_EXPORT_QUAD    float32 [ncells][8] M, Qxx Qyy Qzz, Qxy Qxz Qyz, 0
+ *   MIBH_EXPORT_SPOS    float32 [n][4]    sorted x y z m
+ * Synchronises (it reads the current sizes).  Errors: EINVAL, ESTATE. */
+enum {
+    MIBH_EXPORT_KEYS = 0, MIBH_EXPORT_PERM, MIBH_EXPORT_CELLS, MIBH_EXPORT_GROUPS,
+    MIBH_EXPORT_COUNTS, MIBH_EXPORT_MULTIPOLES, MIBH_EXPORT_DELTA, MIBH_EXPORT_MAC,
+    MIBH_EXPORT_QUAD, MIBH_EXPORT_SPOS
+};
+mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes);
+mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes);
+
+/* Stage timing with HIP events on the context's stream, for the sections the
+ * paper times separately (Results section, Fig. 1): sorting (bounding cube,
+ * keys, radix sort), moving (reorder), tree construction (octree, groups),
+ * multipole moments, MAC preparation and the tree traverse (walk kernel).
+ * mibh_profile_begin(ctx, max_steps) starts recording one set of events per
+ * step (a step ends at compute_forces) for up to max_steps steps;
+ * mibh_profile_read synchronises, writes ms[step][MIBH_NSTAGES] for the
+ * recorded steps, sets *nsteps and stops recording.  Errors: EINVAL, EHIP. */
+enum {
+    MIBH_STAGE_SORT = 0, MIBH_STAGE_MOVE, MIBH_STAGE_BUILD, MIBH_STAGE_MULTIPOLES, MIBH_STAGE_MACPREP,
+    MIBH_STAGE_WALK, MIBH_NSTAGES
+};
+mibh_status mibh_profile_begin(mibh_ctx *ctx, int max_steps);
+mibh_status mibh_profile_read(mibh_ctx *ctx, float *ms, int max_steps, int *nsteps);
+
+/* Human-readable status name, and the calling thread's last error message. */
+const char *mibh_status_string(mibh_status s);
+const char *mibh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIBH_H */

@@ -1,0 +1,474 @@
+// Host side of the C ABI declared in include/mibh.h: workspace layout,
+// argument checks, launch sequencing on the caller's stream.
+#include "mibh.h"
+#include "mibh_device.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+using namespace mibh;
+
+struct mibh_ctx {
+    mibh_params p;
+    int64_t n_max;
+    hipStream_t stream;
+    int device;
+    Buffers b;
+    int state;  // 0 nothing, 1 tree built, 2 multipoles, 3 forces
+    int64_t n;
+    const float *pos, *mass;
+    float *acc, *pot;
+    double *h_energy;  // pinned 2 doubles for mibh_energy
+    double *d_energy;  // 2 doubles in the workspace
+    // stage events: MIBH_NSTAGES + 1 per profiled step
+    hipEvent_t *events;
+    int prof_max, prof_step;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+mibh_status fail(mibh_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+mibh_status hip_fail(hipError_t e, const char *where) {
+    return fail(MIBH_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, where)                         \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int DEFAULT_WALK_WAVES = 4096;  // 16 per compute unit on 256 CUs
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+bool params_valid(const mibh_params &p) {
+    return p.ncrit >= 1 && p.group_cap >= p.ncrit && p.group_cap <= 64 && p.eps2 >= 0.0f &&
+           isfinite(p.eps2) && isfinite(p.G) && (p.precision == MIBH_PLAIN || p.precision == MIBH_KAHAN) &&
+           p.walk_waves >= 0 && p.walk_waves <= (1 << 20) && p.pc_cap >= 64 && p.pp_cap >= 64 &&
+           p.pc_cap <= (1 << 24) && p.pp_cap <= (1 << 24);
+}
+
+// Assigns every buffer of the layout from `base` (nullptr: sizing only) and
+// returns the total bytes.
+size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *ptr = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return ptr;
+    };
+    const size_t n = (size_t)n_max;
+    const size_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    const size_t nblk = (n + BUILD_THREADS - 1) / BUILD_THREADS;
+    // leaves are disjoint and non-empty (<= n); internal cells hold > ncrit
+    // particles each and every particle has at most 20 internal ancestors
+    const size_t cap_cells = n + (20 * n) / (size_t)(p.ncrit + 1) + 2;
+    const size_t waves = p.walk_waves ? (size_t)p.walk_waves : DEFAULT_WALK_WAVES;
+    Buffers t;
+    t.hdr = (Header *)take(sizeof(Header));
+    t.bbox_part = (float *)take(sizeof(float) * 8 * BBOX_BLOCKS);
+    t.keys[0] = (uint64_t *)take(8 * n);
+    t.keys[1] = (uint64_t *)take(8 * n);
+    t.vals[0] = (uint32_t *)take(4 * n);
+    t.vals[1] = (uint32_t *)take(4 * n);
+    t.hist = (uint32_t *)take(4 * RADIX * ntiles);
+    t.btot = (uint32_t *)take(4 * RADIX);
+    t.spos = (float4 *)take(16 * n);
+    t.cl = (int8_t *)take(n);
+    t.lvinfo = (uchar4 *)take(4 * n);
+    t.blkcnt = (uint32_t *)take(4 * NCOUNTERS * nblk);
+    t.ctot = (uint32_t *)take(4 * NCOUNTERS);
+    t.topo = (uint4 *)take(16 * cap_cells);
+    t.mp = (double *)take(80 * cap_cells);
+    t.delta = (double *)take(8 * cap_cells);
+    t.cmac = (float4 *)take(16 * cap_cells);
+    t.ceval = (float4 *)take(32 * cap_cells);
+    t.groups = (uint2 *)take(8 * n);
+    t.gcounts = (uint2 *)take(8 * n);
+    t.wstack = (uint32_t *)take(4 * (size_t)STACK_CAP * waves);
+    t.wpc = (uint32_t *)take(4 * (size_t)p.pc_cap * waves);
+    t.wpp = (uint32_t *)take(4 * (size_t)p.pp_cap * waves);
+    t.epart = (double *)take(8 * 2 * ENERGY_BLOCKS + 16);
+    t.cap_cells = (unsigned)cap_cells;
+    t.n_max = (unsigned)n_max;
+    t.ntiles_max = (unsigned)ntiles;
+    t.nblk_max = (unsigned)nblk;
+    t.walk_waves = (unsigned)waves;
+    t.pc_cap = (unsigned)p.pc_cap;
+    t.pp_cap = (unsigned)p.pp_cap;
+    if (b) *b = t;
+    return off;
+}
+
+mibh_status check_ctx(mibh_ctx *ctx) {
+    if (!ctx) return fail(MIBH_EINVAL, "null context");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return MIBH_OK;
+}
+
+mibh_status read_header(mibh_ctx *ctx, Header *h) {
+    HIP_TRY(hipMemcpyAsync(h, ctx->b.hdr, sizeof(Header), hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync(header)");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return MIBH_OK;
+}
+
+mibh_status flags_status(unsigned flags) {
+    if (flags & (FLAG_NONFINITE | FLAG_NEGMASS))
+        return fail(MIBH_ENONFINITE, "input has a non-finite position or mass, or a negative mass");
+    if (flags & (FLAG_STACK | FLAG_CELLCAP)) return fail(MIBH_EOVERFLOW, "device capacity exceeded (flags %u)", flags);
+    return MIBH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mibh_default_params(mibh_params *p) {
+    if (!p) return;
+    p->ncrit = 16;
+    p->group_cap = 64;
+    p->eps2 = 0.0f;
+    p->G = 1.0f;
+    p->precision = MIBH_PLAIN;
+    p->walk_waves = 0;
+    p->pc_cap = 8192;
+    p->pp_cap = 4096;
+}
+
+size_t mibh_workspace_bytes(int64_t n_max, const mibh_params *pp) {
+    mibh_params p;
+    if (pp) p = *pp; else mibh_default_params(&p);
+    if (n_max < 1 || n_max >= ((int64_t)1 << 31) || !params_valid(p)) return 0;
+    return layout(n_max, p, nullptr, nullptr);
+}
+
+mibh_status mibh_create(const mibh_params *pp, int64_t n_max, void *d_workspace, size_t workspace_bytes,
+                        void *stream, mibh_ctx **out) {
+    if (!out) return fail(MIBH_EINVAL, "null output pointer");
+    *out = nullptr;
+    mibh_params p;
+    if (pp) p = *pp; else mibh_default_params(&p);
+    if (!params_valid(p)) return fail(MIBH_EINVAL, "invalid parameters");
+    if (n_max < 1 || n_max >= ((int64_t)1 << 31)) return fail(MIBH_EINVAL, "n_max out of range");
+    if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0)
+        return fail(MIBH_EINVAL, "workspace must be non-null and 256-byte aligned");
+    const size_t need = layout(n_max, p, nullptr, nullptr);
+    if (workspace_bytes < need)
+        return fail(MIBH_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+    mibh_ctx *c = new (std::nothrow) mibh_ctx();
+    if (!c) return fail(MIBH_ENOMEM, "host allocation failed");
+    c->p = p;
+    c->n_max = n_max;
+    c->stream = (hipStream_t)stream;
+    c->state = 0;
+    c->n = 0;
+    c->pos = c->mass = nullptr;
+    c->acc = c->pot = nullptr;
+    c->events = nullptr;
+    c->prof_max = c->prof_step = 0;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDevice");
+    }
+    layout(n_max, p, (char *)d_workspace, &c->b);
+    c->d_energy = c->b.epart + 2 * ENERGY_BLOCKS;
+    e = hipHostMalloc((void **)&c->h_energy, 2 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipHostMalloc");
+    }
+    *out = c;
+    return MIBH_OK;
+}
+
+static void free_events(mibh_ctx *ctx) {
+    if (!ctx->events) return;
+    for (int i = 0; i < ctx->prof_max * (MIBH_NSTAGES + 1); i++)
+        if (ctx->events[i]) (void)hipEventDestroy(ctx->events[i]);
+    free(ctx->events);
+    ctx->events = nullptr;
+    ctx->prof_max = ctx->prof_step = 0;
+}
+
+// Records the event that ends stage `stage` (stage -1: the step's start).
+static mibh_status mark(mibh_ctx *ctx, int stage) {
+    if (!ctx->events || ctx->prof_step >= ctx->prof_max) return MIBH_OK;
+    hipEvent_t e = ctx->events[ctx->prof_step * (MIBH_NSTAGES + 1) + stage + 1];
+    HIP_TRY(hipEventRecord(e, ctx->stream), "hipEventRecord");
+    return MIBH_OK;
+}
+
+mibh_status mibh_destroy(mibh_ctx *ctx) {
+    if (!ctx) return MIBH_OK;
+    (void)hipSetDevice(ctx->device);
+    free_events(ctx);
+    if (ctx->h_energy) (void)hipHostFree(ctx->h_energy);
+    delete ctx;
+    return MIBH_OK;
+}
+
+mibh_status mibh_build_tree(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!d_pos || !d_mass) return fail(MIBH_EINVAL, "null input pointer");
+    if (n < 1 || n > ctx->n_max) return fail(MIBH_EINVAL, "n = %lld outside [1, %lld]", (long long)n,
+                                             (long long)ctx->n_max);
+    const unsigned un = (unsigned)n;
+    hipStream_t s = ctx->stream;
+    if ((st = mark(ctx, -1))) return st;
+    HIP_TRY(launch_bbox(ctx->b, d_pos, d_mass, un, s), "bbox");
+    HIP_TRY(launch_keys(ctx->b, d_pos, un, s), "keys");
+    HIP_TRY(launch_sort(ctx->b, un, s), "sort");
+    if ((st = mark(ctx, MIBH_STAGE_SORT))) return st;
+    HIP_TRY(launch_reorder(ctx->b, d_pos, d_mass, un, s), "reorder");
+    if ((st = mark(ctx, MIBH_STAGE_MOVE))) return st;
+    HIP_TRY(launch_build(ctx->b, un, ctx->p.ncrit, ctx->p.group_cap, s), "build");
+    if ((st = mark(ctx, MIBH_STAGE_BUILD))) return st;
+    ctx->n = n;
+    ctx->pos = d_pos;
+    ctx->mass = d_mass;
+    ctx->state = 1;
+    return MIBH_OK;
+}
+
+mibh_status mibh_compute_multipoles(mibh_ctx *ctx) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->state < 1) return fail(MIBH_ESTATE, "compute_multipoles before build_tree");
+    HIP_TRY(launch_multipoles(ctx->b, ctx->stream), "multipoles");
+    if ((st = mark(ctx, MIBH_STAGE_MULTIPOLES))) return st;
+    ctx->state = 2;
+    return MIBH_OK;
+}
+
+mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float *d_pot) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->state < 2) return fail(MIBH_ESTATE, "compute_forces before compute_multipoles");
+    if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
+    if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
+    const double inv_theta = 1.0 / (double)theta;
+    HIP_TRY(launch_mac_prep(ctx->b, inv_theta, ctx->stream), "mac_prep");
+    if ((st = mark(ctx, MIBH_STAGE_MACPREP))) return st;
+    HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, ctx->p.eps2, ctx->p.G, ctx->p.precision, d_acc, d_pot,
+                        ctx->stream),
+            "walk");
+    if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;
+    if (ctx->events && ctx->prof_step < ctx->prof_max) ctx->prof_step++;
+    ctx->acc = d_acc;
+    ctx->pot = d_pot;
+    ctx->state = 3;
+    return MIBH_OK;
+}
+
+mibh_status mibh_forces(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n, float theta,
+                        float *d_acc, float *d_pot) {
+    if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
+    if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
+    mibh_status st = mibh_build_tree(ctx, d_pos, d_mass, n);
+    if (st) return st;
+    if ((st = mibh_compute_multipoles(ctx))) return st;
+    return mibh_compute_forces(ctx, theta, d_acc, d_pot);
+}
+
+mibh_status mibh_sync(mibh_ctx *ctx) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->state < 1) {
+        HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        return MIBH_OK;
+    }
+    Header h;
+    if ((st = read_header(ctx, &h))) return st;
+    return flags_status(h.flags);
+}
+
+mibh_status mibh_stats(mibh_ctx *ctx, mibh_stats_t *out) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!out) return fail(MIBH_EINVAL, "null output pointer");
+    if (ctx->state < 1) return fail(MIBH_ESTATE, "stats before build_tree");
+    Header h;
+    if ((st = read_header(ctx, &h))) return st;
+    memset(out, 0, sizeof(*out));
+    out->n = ctx->n;
+    out->ncells = h.ncells;
+    out->ngroups = h.ngroups;
+    out->root_k = h.k;
+    out->flags = h.flags;
+    int depth = 0;
+    for (int l = 0; l <= KEY_LEVELS; l++)
+        if (h.lvl_begin[l + 1] > h.lvl_begin[l]) depth = l;
+    out->depth = depth;
+    // leaves and interaction counts from the exported arrays (host side, exact integers)
+    const size_t ncell = h.ncells <= ctx->b.cap_cells ? h.ncells : ctx->b.cap_cells;
+    uint4 *topo = (uint4 *)malloc(ncell * sizeof(uint4) + 1);
+    uint2 *grp = (uint2 *)malloc((size_t)h.ngroups * sizeof(uint2) + 1);
+    uint2 *cnt = (uint2 *)malloc((size_t)h.ngroups * sizeof(uint2) + 1);
+    if (!topo || !grp || !cnt) {
+        free(topo); free(grp); free(cnt);
+        return fail(MIBH_ENOMEM, "host allocation failed");
+    }
+    hipError_t e = hipMemcpy(topo, ctx->b.topo, ncell * sizeof(uint4), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(grp, ctx->b.groups, (size_t)h.ngroups * sizeof(uint2), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ctx->state >= 3)
+        e = hipMemcpy(cnt, ctx->b.gcounts, (size_t)h.ngroups * sizeof(uint2), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        free(topo); free(grp); free(cnt);
+        return hip_fail(e, "hipMemcpy(stats)");
+    }
+    for (size_t c = 0; c < ncell; c++) out->nleaves += (topo[c].w & 255u) == 0;
+    if (ctx->state >= 3)
+        for (size_t g = 0; g < h.ngroups; g++) {
+            const uint64_t gn = grp[g].y & 255u;
+            out->sum_pc += gn * cnt[g].x;
+            out->sum_pp += gn * cnt[g].y;
+        }
+    free(topo); free(grp); free(cnt);
+    return flags_status(h.flags);
+}
+
+mibh_status mibh_energy(mibh_ctx *ctx, const float *d_vel, double *T, double *W) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->state < 3) return fail(MIBH_ESTATE, "energy before compute_forces");
+    if (!T || !W) return fail(MIBH_EINVAL, "null output pointer");
+    HIP_TRY(launch_energy(ctx->b, ctx->mass, ctx->pot, d_vel, (unsigned)ctx->n, ctx->d_energy, ctx->stream),
+            "energy");
+    HIP_TRY(hipMemcpyAsync(ctx->h_energy, ctx->d_energy, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync(energy)");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    *T = ctx->h_energy[0];
+    *W = ctx->h_energy[1];
+    Header h;
+    if ((st = read_header(ctx, &h))) return st;
+    return flags_status(h.flags);
+}
+
+mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!bytes) return fail(MIBH_EINVAL, "null output pointer");
+    if (ctx->state < 1) return fail(MIBH_ESTATE, "export before build_tree");
+    Header h;
+    if ((st = read_header(ctx, &h))) return st;
+    const size_t n = (size_t)ctx->n;
+    const size_t nc = h.ncells <= ctx->b.cap_cells ? h.ncells : ctx->b.cap_cells, ng = h.ngroups;
+    switch (what) {
+        case MIBH_EXPORT_KEYS: *bytes = 8 * n; break;
+        case MIBH_EXPORT_PERM: *bytes = 4 * n; break;
+        case MIBH_EXPORT_CELLS: *bytes = 16 * nc; break;
+        case MIBH_EXPORT_GROUPS: *bytes = 8 * ng; break;
+        case MIBH_EXPORT_COUNTS: *bytes = 8 * ng; break;
+        case MIBH_EXPORT_MULTIPOLES: *bytes = 80 * nc; break;
+        case MIBH_EXPORT_DELTA: *bytes = 8 * nc; break;
+        case MIBH_EXPORT_MAC: *bytes = 16 * nc; break;
+        case MIBH_EXPORT_QUAD: *bytes = 32 * nc; break;
+        case MIBH_EXPORT_SPOS: *bytes = 16 * n; break;
+        default: return fail(MIBH_EINVAL, "unknown export %d", what);
+    }
+    return MIBH_OK;
+}
+
+mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
+    size_t need = 0;
+    mibh_status st = mibh_export_bytes(ctx, what, &need);
+    if (st) return st;
+    if (!d_dst) return fail(MIBH_EINVAL, "null destination");
+    if (bytes < need) return fail(MIBH_EINVAL, "destination too small: %zu < %zu", bytes, need);
+    if ((what == MIBH_EXPORT_COUNTS || what == MIBH_EXPORT_MAC) && ctx->state < 3)
+        return fail(MIBH_ESTATE, "export of walk data before compute_forces");
+    if ((what == MIBH_EXPORT_MULTIPOLES || what == MIBH_EXPORT_DELTA || what == MIBH_EXPORT_QUAD) &&
+        ctx->state < 2)
+        return fail(MIBH_ESTATE, "export of multipoles before compute_multipoles");
+    const void *src = nullptr;
+    switch (what) {
+        case MIBH_EXPORT_KEYS: src = ctx->b.keys[0]; break;
+        case MIBH_EXPORT_PERM: src = ctx->b.vals[0]; break;
+        case MIBH_EXPORT_CELLS: src = ctx->b.topo; break;
+        case MIBH_EXPORT_GROUPS: src = ctx->b.groups; break;
+        case MIBH_EXPORT_COUNTS: src = ctx->b.gcounts; break;
+        case MIBH_EXPORT_MULTIPOLES: src = ctx->b.mp; break;
+        case MIBH_EXPORT_DELTA: src = ctx->b.delta; break;
+        case MIBH_EXPORT_MAC: src = ctx->b.cmac; break;
+        case MIBH_EXPORT_QUAD: src = ctx->b.ceval; break;
+        case MIBH_EXPORT_SPOS: src = ctx->b.spos; break;
+    }
+    if (need) HIP_TRY(hipMemcpyAsync(d_dst, src, need, hipMemcpyDeviceToDevice, ctx->stream), "hipMemcpyAsync(export)");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return MIBH_OK;
+}
+
+mibh_status mibh_profile_begin(mibh_ctx *ctx, int max_steps) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (max_steps < 1 || max_steps > 100000) return fail(MIBH_EINVAL, "max_steps out of range");
+    free_events(ctx);
+    const int ne = max_steps * (MIBH_NSTAGES + 1);
+    ctx->events = (hipEvent_t *)calloc(ne, sizeof(hipEvent_t));
+    if (!ctx->events) return fail(MIBH_ENOMEM, "host allocation failed");
+    ctx->prof_max = max_steps;
+    ctx->prof_step = 0;
+    for (int i = 0; i < ne; i++) {
+        hipError_t e = hipEventCreate(&ctx->events[i]);
+        if (e != hipSuccess) {
+            free_events(ctx);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    return MIBH_OK;
+}
+
+mibh_status mibh_profile_read(mibh_ctx *ctx, float *ms, int max_steps, int *nsteps) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!ms || !nsteps) return fail(MIBH_EINVAL, "null output pointer");
+    if (!ctx->events) return fail(MIBH_EINVAL, "profiling was not started");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    const int ns = ctx->prof_step < max_steps ? ctx->prof_step : max_steps;
+    for (int k = 0; k < ns; k++)
+        for (int s = 0; s < MIBH_NSTAGES; s++) {
+            float t = 0.0f;
+            hipEvent_t *e = ctx->events + k * (MIBH_NSTAGES + 1);
+            HIP_TRY(hipEventElapsedTime(&t, e[s], e[s + 1]), "hipEventElapsedTime");
+            ms[k * MIBH_NSTAGES + s] = t;
+        }
+    *nsteps = ns;
+    free_events(ctx);
+    return MIBH_OK;
+}
+
+const char *mibh_status_string(mibh_status s) {
+    switch (s) {
+        case MIBH_OK: return "MIBH_OK";
+        case MIBH_EINVAL: return "MIBH_EINVAL";
+        case MIBH_ENOMEM: return "MIBH_ENOMEM";
+        case MIBH_EHIP: return "MIBH_EHIP";
+        case MIBH_ESTATE: return "MIBH_ESTATE";
+        case MIBH_EOVERFLOW: return "MIBH_EOVERFLOW";
+        case MIBH_ENONFINITE: return "MIBH_ENONFINITE";
+    }
+    return "MIBH_UNKNOWN";
+}
+
+const char *mibh_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal definitions shared by the HIP kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mibh {
+
+constexpr int KEY_LEVELS = 20;          // 20 bits per axis, 60-bit keys, levels 0..20
+constexpr int NCOUNTERS = 22;           // per-block counters of the build: levels 0..20, groups
+
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int SORT_PASSES = 8;          // 64 bits in 8-bit digits (bits 60..63 are zero)
+constexpr int SORT_THREADS = 256;       // 4 waves
+constexpr int SORT_ITEMS = 16;          // keys per thread per tile
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
+
+constexpr int BUILD_THREADS = 256;      // particles per build block
+constexpr int MAX_WINDOW = 64;          // largest group_cap (halo of the build window)
+constexpr int BBOX_BLOCKS = 1024;
+constexpr int ENERGY_BLOCKS = 1024;
+constexpr int ENERGY_THREADS = 256;
+
+// Walk: one wave per workgroup; cell stack bound (see walk kernel): every
+// traversal step pushes at most 64*8 children and at most one step's pushes
+// per level are on the stack at any time, so 1 + 20*512 entries suffice.
+constexpr unsigned STACK_CAP = 21u * 512u;
+
+enum : unsigned {
+    FLAG_NONFINITE = 1u,
+    FLAG_NEGMASS = 2u,
+    FLAG_STACK = 4u,
+    FLAG_CELLCAP = 8u,
+};
+
+// Device-resident per-context state, rewritten by every build.
+struct Header {
+    float lo[4];            // root cube corner (x, y, z)
+    int k;                  // root cube side 2^k
+    unsigned flags;
+    unsigned n;
+    unsigned ncells;
+    unsigned ngroups;
+    unsigned walk_next;     // persistent walk queue head
+    unsigned lvl_begin[24]; // cells of level l are [lvl_begin[l], lvl_begin[l+1]), l = 0..20
+    unsigned long long sum_pc, sum_pp;
+    unsigned pad[8];
+};
+
+// Device pointers carved from the caller's workspace.
+struct Buffers {
+    Header *hdr;
+    float *bbox_part;       // [BBOX_BLOCKS][8]
+    uint64_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *hist;         // [RADIX][ntiles]
+    uint32_t *btot;         // [RADIX]
+    float4 *spos;           // sorted x, y, z, m
+    int8_t *cl;             // common leading octal digits with the previous key (-1 at 0)
+    uchar4 *lvinfo;         // per particle: first level started, leaf level, group level, group start
+    uint32_t *blkcnt;       // [NCOUNTERS][nblk]
+    uint32_t *ctot;         // [NCOUNTERS]
+    uint4 *topo;            // cells: first, count, child_first, level<<8 | nchild
+    double *mp;             // cells: [10] M, com xyz, S xx yy zz xy xz yz
+    double *delta;          // cells: |com - centre|
+    float4 *cmac;           // cells: com32 xyz, r_open^2
+    float4 *ceval;          // cells: [2] (M, Qxx, Qyy, Qzz), (Qxy, Qxz, Qyz, 0)
+    uint2 *groups;          // first, level<<8 | count
+    uint2 *gcounts;         // n_pc, n_pp
+    uint32_t *wstack;       // per walk wave: STACK_CAP
+    uint32_t *wpc;          // per walk wave: pc_cap
+    uint32_t *wpp;          // per walk wave: pp_cap
+    double *epart;          // energy partials [ENERGY_BLOCKS][2]
+    unsigned cap_cells, n_max, ntiles_max, nblk_max;
+    unsigned walk_waves, pc_cap, pp_cap;
+};
+
+// Host launchers (kernels live in the .hip files).
+hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, hipStream_t s);
+hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, hipStream_t s);
+hipError_t launch_sort(const Buffers &b, unsigned n, hipStream_t s);
+hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n,
+                          hipStream_t s);
+hipError_t launch_build(const Buffers &b, unsigned n, int ncrit, int gcap, hipStream_t s);
+hipError_t launch_multipoles(const Buffers &b, hipStream_t s);
+hipError_t launch_mac_prep(const Buffers &b, double inv_theta, hipStream_t s);
+hipError_t launch_walk(const Buffers &b, unsigned n, float eps2, float G, int precision,
+                       float *acc, float *pot, hipStream_t s);
+hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
+                         unsigned n, double *d_out2, hipStream_t s);
+
+}  // namespace mibh

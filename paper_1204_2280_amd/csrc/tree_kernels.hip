@@ -1,0 +1,817 @@
+// Tree pipeline of the force step on gfx950: bounding cube, Morton keys,
+// stable LSD radix sort, reorder ("moving"), breadth-first sparse octree and
+// groups ("tree-construction"), float64 multipole moments and the per-theta
+// opening radii.  The paper's parts are named in its Results section; the
+// kernels here are this library's own design for CDNA4 (wave64 ballots,
+// LDS-staged windows, no host synchronisation inside a step).
+#include "mibh_device.h"
+
+#include <math.h>
+
+namespace mibh {
+
+// --------------------------------------------------------------------------
+// wave64 helpers
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned lane64() { return __lane_id(); }
+
+// Number of set bits of mask in lanes below this one.
+__device__ __forceinline__ unsigned rank_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// Lanes (among those in `active`) holding the same 8-bit digit as this lane.
+__device__ __forceinline__ unsigned long long match_digit(unsigned d, unsigned long long active) {
+    unsigned long long m = active;
+#pragma unroll
+    for (int b = 0; b < RADIX_BITS; b++) {
+        const bool bit = (d >> b) & 1u;
+        const unsigned long long v = __ballot(bit);
+        m &= bit ? v : ~v;
+    }
+    return m;
+}
+
+// Inclusive scan over the 64 lanes of a wave.
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned y = __shfl_up(v, o, 64);
+        if (lane64() >= (unsigned)o) v += y;
+    }
+    return v;
+}
+
+// Exclusive scan of a block of NT threads (NT multiple of 64, <= 1024).
+template <int NT>
+__device__ __forceinline__ unsigned block_excl_scan(unsigned v, unsigned *s_wave, unsigned *total) {
+    const unsigned w = threadIdx.x >> 6;
+    const unsigned inc = wave_incl_scan(v);
+    if (lane64() == 63) s_wave[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned run = 0;
+        for (int i = 0; i < NT / 64; i++) {
+            unsigned t = s_wave[i];
+            s_wave[i] = run;
+            run += t;
+        }
+        s_wave[NT / 64] = run;
+    }
+    __syncthreads();
+    const unsigned r = s_wave[w] + inc - v;
+    *total = s_wave[NT / 64];
+    __syncthreads();
+    return r;
+}
+
+// Morton bit spreading: bit b of v (20 bits) moves to bit 3b.
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// Inverse of spread3: gathers bits 0, 3, 6, ... into a dense integer.
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+// Number of leading octal digits two 60-bit keys share (0..20).
+__device__ __forceinline__ int shared_digits(uint64_t a, uint64_t b) {
+    const uint64_t x = a ^ b;
+    if (x == 0) return KEY_LEVELS;
+    return (__clzll((long long)x) - 4) / 3;
+}
+
+// First index j > i whose key differs from key i in the first `lev` octal
+// digits (n if none): galloping search over the sorted keys.
+__device__ __forceinline__ unsigned run_end(const uint64_t *__restrict__ keys, unsigned n, unsigned i,
+                                            int lev) {
+    if (lev == 0) return n;
+    const int sh = 3 * (KEY_LEVELS - lev);
+    const uint64_t p = keys[i] >> sh;
+    unsigned lo = i, step = 1, hi = i + 1;
+    while (hi < n && (keys[hi] >> sh) == p) {
+        lo = hi;
+        step <<= 1;
+        hi = (n - i > step) ? i + step : n;
+    }
+    if (hi > n) hi = n;
+    while (hi - lo > 1) {
+        const unsigned mid = lo + (hi - lo) / 2;
+        if ((keys[mid] >> sh) == p) lo = mid; else hi = mid;
+    }
+    return hi;
+}
+
+// --------------------------------------------------------------------------
+// Bounding cube
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ pos,
+                                                      const float *__restrict__ mass, unsigned n,
+                                                      float *__restrict__ part) {
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    unsigned flags = 0;
+    for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const size_t b = (size_t)i * 3;
+        const float x[3] = {pos[b], pos[b + 1], pos[b + 2]};
+        const float m = mass[i];
+        if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(m))) flags |= FLAG_NONFINITE;
+        if (m < 0.0f) flags |= FLAG_NEGMASS;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            mn[a] = fminf(mn[a], x[a]);
+            mx[a] = fmaxf(mx[a], x[a]);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+        }
+        flags |= __shfl_xor(flags, o, 64);
+    }
+    __shared__ float s[4][8];
+    const unsigned w = threadIdx.x >> 6;
+    if (lane64() == 0) {
+        for (int a = 0; a < 3; a++) { s[w][a] = mn[a]; s[w][3 + a] = mx[a]; }
+        s[w][6] = __uint_as_float(flags);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; v++) {
+            for (int a = 0; a < 3; a++) {
+                s[0][a] = fminf(s[0][a], s[v][a]);
+                s[0][3 + a] = fmaxf(s[0][3 + a], s[v][3 + a]);
+            }
+            s[0][6] = __uint_as_float(__float_as_uint(s[0][6]) | __float_as_uint(s[v][6]));
+        }
+        for (int a = 0; a < 7; a++) part[blockIdx.x * 8 + a] = s[0][a];
+    }
+}
+
+// Root cube: corner = per-axis minimum; side 2^k with 2^k > largest extent
+// (frexp of the float64 extent), k = 0 for a zero extent.  Resets the header.
+__global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ part, unsigned n,
+                                                    Header *__restrict__ hdr) {
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    unsigned flags = 0;
+    for (unsigned b = threadIdx.x; b < BBOX_BLOCKS; b += 256) {
+        for (int a = 0; a < 3; a++) {
+            mn[a] = fminf(mn[a], part[b * 8 + a]);
+            mx[a] = fmaxf(mx[a], part[b * 8 + 3 + a]);
+        }
+        flags |= __float_as_uint(part[b * 8 + 6]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int a = 0; a < 3; a++) {
+            mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+        }
+        flags |= __shfl_xor(flags, o, 64);
+    }
+    __shared__ float s[4][8];
+    const unsigned w = threadIdx.x >> 6;
+    if (lane64() == 0) {
+        for (int a = 0; a < 3; a++) { s[w][a] = mn[a]; s[w][3 + a] = mx[a]; }
+        s[w][6] = __uint_as_float(flags);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; v++) {
+            for (int a = 0; a < 3; a++) {
+                s[0][a] = fminf(s[0][a], s[v][a]);
+                s[0][3 + a] = fmaxf(s[0][3 + a], s[v][3 + a]);
+            }
+            s[0][6] = __uint_as_float(__float_as_uint(s[0][6]) | __float_as_uint(s[v][6]));
+        }
+        flags = __float_as_uint(s[0][6]);
+        double ext = 0.0;
+        for (int a = 0; a < 3; a++) {
+            const double e = (double)s[0][3 + a] - (double)s[0][a];
+            if (e > ext) ext = e;
+        }
+        int k = 0;
+        if (ext > 0.0) frexp(ext, &k);
+        if (flags & FLAG_NONFINITE) {  // keep every later index computation tame
+            k = 0;
+            for (int a = 0; a < 3; a++) s[0][a] = 0.0f;
+        }
+        for (int a = 0; a < 3; a++) hdr->lo[a] = s[0][a];
+        hdr->lo[3] = 0.0f;
+        hdr->k = k;
+        hdr->flags = flags;
+        hdr->n = n;
+        hdr->ncells = 0;
+        hdr->ngroups = 0;
+        hdr->walk_next = 0;
+        hdr->sum_pc = 0;
+        hdr->sum_pp = 0;
+        for (int l = 0; l < 24; l++) hdr->lvl_begin[l] = 0;
+    }
+}
+
+hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, hipStream_t s) {
+    hipLaunchKernelGGL(k_bbox_partial, dim3(BBOX_BLOCKS), dim3(256), 0, s, pos, mass, n, b.bbox_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, b.bbox_part, n, b.hdr);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Morton keys: q_a = min(floor((x_a - lo_a) 2^(20-k)), 2^20 - 1), bits of
+// q_x, q_y, q_z at 3b+2, 3b+1, 3b.
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ pos, unsigned n,
+                                              const Header *__restrict__ hdr,
+                                              uint64_t *__restrict__ keys) {
+    const unsigned i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    const double s = ldexp(1.0, KEY_LEVELS - hdr->k);
+    uint64_t q[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        double f = floor(((double)pos[(size_t)i * 3 + a] - (double)hdr->lo[a]) * s);
+        if (!(f >= 0.0)) f = 0.0;
+        if (f > 1048575.0) f = 1048575.0;
+        q[a] = (uint64_t)f;
+    }
+    keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+}
+
+hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, s, pos, n, b.hdr, b.keys[0]);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Stable LSD radix sort of (key, index), 8-bit digits, reduce-then-scan:
+// per-tile digit histograms -> per-digit scan over tiles -> stable scatter.
+// Ranks inside a tile come from wave64 digit matching (8 ballots) processed
+// in key order, so equal digits keep their input order.
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__restrict__ keys,
+                                                             unsigned n, int shift,
+                                                             uint32_t *__restrict__ hist,
+                                                             unsigned ntiles) {
+    __shared__ uint32_t h[SORT_THREADS / 64][RADIX];
+    const unsigned w = threadIdx.x >> 6, ln = lane64();
+    for (unsigned j = threadIdx.x; j < (SORT_THREADS / 64) * RADIX; j += SORT_THREADS) (&h[0][0])[j] = 0;
+    __syncthreads();
+    const unsigned base = blockIdx.x * SORT_TILE + w * (64 * SORT_ITEMS);
+    for (int t = 0; t < SORT_ITEMS; t++) {
+        const unsigned idx = base + t * 64 + ln;
+        const bool valid = idx < n;
+        const unsigned d = valid ? (unsigned)(keys[idx] >> shift) & (RADIX - 1) : 0u;
+        const unsigned long long peers = match_digit(d, __ballot(valid));
+        if (valid && ln == (unsigned)(__ffsll((long long)peers) - 1)) h[w][d] += __popcll(peers);
+    }
+    __syncthreads();
+    for (unsigned d = threadIdx.x; d < RADIX; d += SORT_THREADS) {
+        unsigned s = 0;
+        for (int v = 0; v < SORT_THREADS / 64; v++) s += h[v][d];
+        hist[(size_t)d * ntiles + blockIdx.x] = s;
+    }
+}
+
+// One block per digit: exclusive scan of its row over tiles; row total to btot.
+__global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist, unsigned ntiles,
+                                                    uint32_t *__restrict__ btot) {
+    __shared__ unsigned s_wave[256 / 64 + 1];
+    uint32_t *row = hist + (size_t)blockIdx.x * ntiles;
+    const unsigned per = (ntiles + 255) / 256;
+    const unsigned b = threadIdx.x * per, e = min(b + per, ntiles);
+    unsigned sum = 0;
+    for (unsigned j = b; j < e; j++) sum += row[j];
+    unsigned total;
+    unsigned run = block_excl_scan<256>(sum, s_wave, &total);
+    for (unsigned j = b; j < e; j++) {
+        const unsigned v = row[j];
+        row[j] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) btot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, unsigned n, int shift, const uint32_t *__restrict__ hist,
+    const uint32_t *__restrict__ btot, unsigned ntiles) {
+    constexpr int NW = SORT_THREADS / 64;
+    __shared__ uint32_t wcnt[NW][RADIX];
+    __shared__ uint32_t gbase[RADIX];
+    __shared__ unsigned s_wave[NW + 1];
+    const unsigned w = threadIdx.x >> 6, ln = lane64();
+    // digit bases: exclusive scan of the digit totals + this tile's offset in the digit row
+    {
+        const unsigned d = threadIdx.x;  // SORT_THREADS == RADIX
+        unsigned total;
+        const unsigned ex = block_excl_scan<SORT_THREADS>(btot[d], s_wave, &total);
+        gbase[d] = ex + hist[(size_t)d * ntiles + blockIdx.x];
+        for (int v = 0; v < NW; v++) wcnt[v][d] = 0;
+    }
+    __syncthreads();
+    const unsigned base = blockIdx.x * SORT_TILE + w * (64 * SORT_ITEMS);
+    uint64_t key[SORT_ITEMS];
+    uint32_t val[SORT_ITEMS], rank[SORT_ITEMS];
+#pragma unroll
+    for (int t = 0; t < SORT_ITEMS; t++) {
+        const unsigned idx = base + t * 64 + ln;
+        const bool valid = idx < n;
+        key[t] = valid ? kin[idx] : 0ull;
+        val[t] = valid ? (vin ? vin[idx] : idx) : 0u;
+        const unsigned d = (unsigned)(key[t] >> shift) & (RADIX - 1);
+        const unsigned long long peers = match_digit(d, __ballot(valid));
+        const unsigned before = wcnt[w][d];
+        rank[t] = before + rank_below(peers);
+        if (valid && ln == (unsigned)(__ffsll((long long)peers) - 1)) wcnt[w][d] = before + __popcll(peers);
+    }
+    __syncthreads();
+    {
+        const unsigned d = threadIdx.x;
+        unsigned run = 0;
+        for (int v = 0; v < NW; v++) {
+            const unsigned c = wcnt[v][d];
+            wcnt[v][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < SORT_ITEMS; t++) {
+        const unsigned idx = base + t * 64 + ln;
+        if (idx < n) {
+            const unsigned d = (unsigned)(key[t] >> shift) & (RADIX - 1);
+            const unsigned p = gbase[d] + wcnt[w][d] + rank[t];
+            kout[p] = key[t];
+            vout[p] = val[t];
+        }
+    }
+}
+
+hipError_t launch_sort(const Buffers &b, unsigned n, hipStream_t s) {
+    const unsigned ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    for (int pass = 0; pass < SORT_PASSES; pass++) {
+        const int src = pass & 1, dst = src ^ 1;
+        const int shift = pass * RADIX_BITS;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src], n, shift,
+                           b.hist, ntiles);
+        hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(256), 0, s, b.hist, ntiles, b.btot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src],
+                           pass == 0 ? (const uint32_t *)nullptr : b.vals[src], b.keys[dst], b.vals[dst],
+                           n, shift, b.hist, b.btot, ntiles);
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Moving: gather (x, y, z, m) into key order; shared digits with the previous key.
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_reorder(const float *__restrict__ pos,
+                                                 const float *__restrict__ mass,
+                                                 const uint64_t *__restrict__ keys,
+                                                 const uint32_t *__restrict__ perm, unsigned n,
+                                                 float4 *__restrict__ spos, int8_t *__restrict__ cl) {
+    const unsigned k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= n) return;
+    const size_t j = perm[k];
+    spos[k] = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], mass[j]);
+    cl[k] = k == 0 ? (int8_t)-1 : (int8_t)shared_digits(keys[k - 1], keys[k]);
+}
+
+hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n,
+                          hipStream_t s) {
+    // after an even number of passes the sorted keys and indices are in buffer 0
+    hipLaunchKernelGGL(k_reorder, dim3((n + 255) / 256), dim3(256), 0, s, pos, mass, b.keys[0], b.vals[0],
+                       n, b.spos, b.cl);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Octree and groups, particle-parallel.
+//
+// With cl(i) the number of leading octal digits keys i-1 and i share, the
+// level-l cell containing particle i starts at i iff cl(i) < l, and it holds
+// more than w particles iff some window of w+1 consecutive particles around i
+// has all its w inner cl values >= l.  So
+//   lstar_w(i) = max over windows [a, a+w] containing i of min cl(a+1..a+w)
+// is the deepest level whose cell around i holds more than w particles.  The
+// leaf of i is at level min(lstar_ncrit + 1, 20) (0 if lstar < 0), its group at
+// min(lstar_gcap + 1, 20); particle i starts the cells of levels
+// cl(i)+1 .. leaf(i).  Cell numbers are per-level ranks, which gives the
+// breadth-first order (level, then key).
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(BUILD_THREADS) void k_build_count(
+    const int8_t *__restrict__ cl, const uint64_t *__restrict__ keys, unsigned n, int ncrit, int gcap,
+    uchar4 *__restrict__ lvinfo, uint32_t *__restrict__ blkcnt, unsigned nblk) {
+    constexpr int H = MAX_WINDOW;
+    constexpr int NW = BUILD_THREADS / 64;
+    __shared__ int8_t s_cl[BUILD_THREADS + 2 * H + 2];
+    __shared__ int8_t s_wn[BUILD_THREADS + H + 1];
+    __shared__ int8_t s_wg[BUILD_THREADS + H + 1];
+    __shared__ uint32_t s_cnt[NW][NCOUNTERS];
+    const unsigned base = blockIdx.x * BUILD_THREADS;
+    for (int j = threadIdx.x; j < BUILD_THREADS + 2 * H + 1; j += BUILD_THREADS) {
+        const long long gi = (long long)base - H + j;
+        s_cl[j] = (gi >= 0 && gi < (long long)n) ? cl[gi] : (int8_t)-1;
+    }
+    __syncthreads();
+    // minimum of cl over each window's inner boundaries, window start a <-> local a - base + H
+    for (int a = threadIdx.x; a < BUILD_THREADS + H; a += BUILD_THREADS) {
+        int mn = 127, mg = 127;
+        for (int d = 1; d <= gcap; d++) {
+            const int v = s_cl[a + d];
+            if (d <= ncrit) mn = min(mn, v);
+            mg = min(mg, v);
+        }
+        s_wn[a] = (int8_t)mn;
+        s_wg[a] = (int8_t)mg;
+    }
+    __syncthreads();
+    const unsigned i = base + threadIdx.x;
+    const bool valid = i < n;
+    const int tl = threadIdx.x + H;
+    int ln = -1, lg = -1;
+    for (int d = 0; d <= gcap; d++) {
+        const int vg = s_wg[tl - d];
+        if (d <= ncrit) ln = max(ln, (int)s_wn[tl - d]);
+        lg = max(lg, vg);
+    }
+    const int leaf = ln < 0 ? 0 : min(ln + 1, KEY_LEVELS);
+    const int glev = lg < 0 ? 0 : min(lg + 1, KEY_LEVELS);
+    const int ci = s_cl[tl];
+    const int clo = ci + 1;
+    bool gstart;
+    unsigned oversized = 0;
+    if (lg >= KEY_LEVELS && valid) {
+        // a run of more than gcap identical keys: cut into chunks of gcap from its start
+        oversized = 1;
+        unsigned start = i;
+        if (ci >= KEY_LEVELS) {
+            const uint64_t key = keys[i];
+            unsigned lo = 0, hi = i;  // first index with keys[index] == key lies in [lo, hi]
+            while (lo < hi) {
+                const unsigned mid = lo + (hi - lo) / 2;
+                if (keys[mid] < key) lo = mid + 1; else hi = mid;
+            }
+            start = lo;
+        }
+        gstart = ((i - start) % (unsigned)gcap) == 0;
+    } else {
+        gstart = ci < glev;
+    }
+    if (valid) lvinfo[i] = make_uchar4((unsigned char)clo, (unsigned char)leaf, (unsigned char)glev,
+                                       (unsigned char)((gstart ? 1 : 0) | (oversized << 1)));
+    const unsigned w = threadIdx.x >> 6;
+    for (int l = 0; l <= KEY_LEVELS; l++) {
+        const unsigned long long b = __ballot(valid && clo <= l && l <= leaf);
+        if (lane64() == 0) s_cnt[w][l] = (uint32_t)__popcll(b);
+    }
+    {
+        const unsigned long long b = __ballot(valid && gstart);
+        if (lane64() == 0) s_cnt[w][NCOUNTERS - 1] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (threadIdx.x < NCOUNTERS) {
+        uint32_t s = 0;
+        for (int v = 0; v < NW; v++) s += s_cnt[v][threadIdx.x];
+        blkcnt[(size_t)threadIdx.x * nblk + blockIdx.x] = s;
+    }
+}
+
+// One block per counter: exclusive scan over blocks, totals to ctot.
+__global__ __launch_bounds__(1024) void k_build_scan(uint32_t *__restrict__ blkcnt, unsigned nblk,
+                                                     uint32_t *__restrict__ ctot) {
+    __shared__ unsigned s_wave[1024 / 64 + 1];
+    uint32_t *row = blkcnt + (size_t)blockIdx.x * nblk;
+    const unsigned per = (nblk + 1023) / 1024;
+    const unsigned b = threadIdx.x * per, e = min(b + per, nblk);
+    unsigned sum = 0;
+    for (unsigned j = b; j < e; j++) sum += row[j];
+    unsigned total;
+    unsigned run = block_excl_scan<1024>(sum, s_wave, &total);
+    for (unsigned j = b; j < e; j++) {
+        const unsigned v = row[j];
+        row[j] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) ctot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
+    const uchar4 *__restrict__ lvinfo, const uint64_t *__restrict__ keys, unsigned n, int gcap,
+    const uint32_t *__restrict__ blkcnt, const uint32_t *__restrict__ ctot, unsigned nblk,
+    Header *__restrict__ hdr, uint4 *__restrict__ topo, uint2 *__restrict__ groups,
+    unsigned cap_cells) {
+    constexpr int NW = BUILD_THREADS / 64;
+    __shared__ uint32_t s_base[NCOUNTERS];   // first cell number of each level; 0 for groups
+    __shared__ uint32_t s_blk[NCOUNTERS];    // this block's offset within each level
+    __shared__ uint32_t s_wpre[NW][NCOUNTERS];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int l = 0; l <= KEY_LEVELS; l++) {
+            s_base[l] = run;
+            run += ctot[l];
+        }
+        s_base[NCOUNTERS - 1] = 0;
+        if (blockIdx.x == 0) {
+            for (int l = 0; l <= KEY_LEVELS; l++) hdr->lvl_begin[l] = s_base[l];
+            hdr->lvl_begin[KEY_LEVELS + 1] = run;
+            hdr->ncells = run;
+            hdr->ngroups = ctot[NCOUNTERS - 1];
+            if (run > cap_cells) atomicOr(&hdr->flags, FLAG_CELLCAP);
+        }
+    }
+    if (threadIdx.x < NCOUNTERS) s_blk[threadIdx.x] = blkcnt[(size_t)threadIdx.x * nblk + blockIdx.x];
+    const unsigned i = blockIdx.x * BUILD_THREADS + threadIdx.x;
+    const bool valid = i < n;
+    const uchar4 info = valid ? lvinfo[i] : make_uchar4(1, 0, 0, 0);
+    const int clo = info.x, leaf = info.y, glev = info.z;
+    const bool gstart = valid && (info.w & 1);
+    const unsigned w = threadIdx.x >> 6;
+    for (int c = 0; c < NCOUNTERS; c++) {
+        const bool pred = c < NCOUNTERS - 1 ? (valid && clo <= c && c <= leaf) : gstart;
+        const unsigned long long b = __ballot(pred);
+        if (lane64() == 0) s_wpre[w][c] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (threadIdx.x < NCOUNTERS) {
+        uint32_t run = 0;
+        for (int v = 0; v < NW; v++) {
+            const uint32_t t = s_wpre[v][threadIdx.x];
+            s_wpre[v][threadIdx.x] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    // cells, deepest level first so that each cell knows its first child's number
+    unsigned next = 0;
+    for (int l = KEY_LEVELS; l >= 0; l--) {
+        const bool pred = valid && clo <= l && l <= leaf;
+        const unsigned long long b = __ballot(pred);
+        if (pred) {
+            const unsigned idx = s_base[l] + s_blk[l] + s_wpre[w][l] + rank_below(b);
+            const unsigned cnt = run_end(keys, n, i, l) - i;
+            const unsigned cf = l < leaf ? next : 0u;
+            if (idx < cap_cells) topo[idx] = make_uint4(i, cnt, cf, ((unsigned)l << 8));
+            next = idx;
+        }
+    }
+    {
+        const unsigned long long b = __ballot(gstart);
+        if (gstart) {
+            const unsigned g = s_blk[NCOUNTERS - 1] + s_wpre[w][NCOUNTERS - 1] + rank_below(b);
+            unsigned cnt;
+            if (info.w & 2) cnt = min((unsigned)gcap, run_end(keys, n, i, KEY_LEVELS) - i);
+            else cnt = run_end(keys, n, i, glev) - i;
+            groups[g] = make_uint2(i, ((unsigned)glev << 8) | cnt);
+        }
+    }
+}
+
+// Children of an internal cell are the consecutive next-level cells that start inside it.
+__global__ __launch_bounds__(256) void k_build_nchild(const Header *__restrict__ hdr,
+                                                      uint4 *__restrict__ topo, unsigned cap_cells) {
+    if (hdr->flags & FLAG_CELLCAP) return;  // cell numbers beyond the capacity were never written
+    const unsigned nc = min(hdr->ncells, cap_cells);
+    for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
+        const uint4 t = topo[c];
+        if (t.z == 0) continue;
+        const unsigned l = t.w >> 8;
+        const unsigned lend = min(hdr->lvl_begin[l + 2], nc);
+        const unsigned end = t.x + t.y;
+        unsigned nch = 0;
+        for (unsigned k = t.z; k < lend && nch < 8; k++) {
+            if (topo[k].x < end) nch++;
+            else break;
+        }
+        reinterpret_cast<unsigned *>(topo)[4 * (size_t)c + 3] = (l << 8) | nch;
+    }
+}
+
+hipError_t launch_build(const Buffers &b, unsigned n, int ncrit, int gcap, hipStream_t s) {
+    const unsigned nblk = (n + BUILD_THREADS - 1) / BUILD_THREADS;
+    hipLaunchKernelGGL(k_build_count, dim3(nblk), dim3(BUILD_THREADS), 0, s, b.cl, b.keys[0], n, ncrit,
+                       gcap, b.lvinfo, b.blkcnt, nblk);
+    hipLaunchKernelGGL(k_build_scan, dim3(NCOUNTERS), dim3(1024), 0, s, b.blkcnt, nblk, b.ctot);
+    hipLaunchKernelGGL(k_build_write, dim3(nblk), dim3(BUILD_THREADS), 0, s, b.lvinfo, b.keys[0], n, gcap,
+                       b.blkcnt, b.ctot, nblk, b.hdr, b.topo, b.groups, b.cap_cells);
+    const unsigned grid = min((b.cap_cells + 255u) / 256u, 4096u);
+    hipLaunchKernelGGL(k_build_nchild, dim3(grid), dim3(256), 0, s, b.hdr, b.topo, b.cap_cells);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Multipole moments, float64, one launch per level from the deepest up.
+//   leaf:     M = sum m, com = (sum fma(m, x, .)) / M, S_ab = sum fma(m d_a, d_b, .)
+//   internal: M = sum M_c, com = (sum fma(M_c, com_c, .)) / M,
+//             S_ab = sum (S_c,ab + (M_c e_a) e_b), e = com_c - com
+//   Q = 3 S - tr(S) I, delta = |com - geometric centre|
+// The operation order is fixed and nothing is contracted except the explicit
+// fma calls, so every run gives the same bits.
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_multipole_level(
+    int lev, const Header *__restrict__ hdr, const uint4 *__restrict__ topo,
+    const float4 *__restrict__ spos, const uint64_t *__restrict__ keys, double *__restrict__ mp,
+    double *__restrict__ delta, float4 *__restrict__ cmac, float4 *__restrict__ ceval,
+    unsigned cap_cells) {
+#pragma clang fp contract(off)
+    if (hdr->flags & FLAG_CELLCAP) return;
+    const unsigned nc = min(hdr->ncells, cap_cells);
+    const unsigned cb = min(hdr->lvl_begin[lev], nc), ce = min(hdr->lvl_begin[lev + 1], nc);
+    const int k = hdr->k;
+    const double lo[3] = {(double)hdr->lo[0], (double)hdr->lo[1], (double)hdr->lo[2]};
+    const double l = ldexp(1.0, k - lev);
+    for (unsigned c = cb + blockIdx.x * 256u + threadIdx.x; c < ce; c += gridDim.x * 256u) {
+        const uint4 t = topo[c];
+        const unsigned nch = t.w & 255u;
+        const uint64_t pre = keys[t.x] >> (3 * (KEY_LEVELS - lev));
+        const double q[3] = {(double)compact3(pre >> 2), (double)compact3(pre >> 1), (double)compact3(pre)};
+        double centre[3];
+        for (int a = 0; a < 3; a++) {
+            const double corner = lo[a] + q[a] * l;
+            centre[a] = corner + 0.5 * l;
+        }
+        double M = 0.0, cm[3] = {0.0, 0.0, 0.0}, com[3];
+        double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (nch == 0) {
+            for (unsigned j = t.x; j < t.x + t.y; j++) {
+                const float4 p = spos[j];
+                const double m = (double)p.w;
+                M = M + m;
+                cm[0] = fma(m, (double)p.x, cm[0]);
+                cm[1] = fma(m, (double)p.y, cm[1]);
+                cm[2] = fma(m, (double)p.z, cm[2]);
+            }
+            for (int a = 0; a < 3; a++) com[a] = M > 0.0 ? cm[a] / M : centre[a];
+            for (unsigned j = t.x; j < t.x + t.y; j++) {
+                const float4 p = spos[j];
+                const double m = (double)p.w;
+                const double dx = (double)p.x - com[0], dy = (double)p.y - com[1], dz = (double)p.z - com[2];
+                S[0] = fma(m * dx, dx, S[0]);
+                S[1] = fma(m * dy, dy, S[1]);
+                S[2] = fma(m * dz, dz, S[2]);
+                S[3] = fma(m * dx, dy, S[3]);
+                S[4] = fma(m * dx, dz, S[4]);
+                S[5] = fma(m * dy, dz, S[5]);
+            }
+        } else {
+            for (unsigned ch = t.z; ch < t.z + nch; ch++) {
+                const double *p = mp + 10 * (size_t)ch;
+                M = M + p[0];
+                cm[0] = fma(p[0], p[1], cm[0]);
+                cm[1] = fma(p[0], p[2], cm[1]);
+                cm[2] = fma(p[0], p[3], cm[2]);
+            }
+            for (int a = 0; a < 3; a++) com[a] = M > 0.0 ? cm[a] / M : centre[a];
+            for (unsigned ch = t.z; ch < t.z + nch; ch++) {
+                const double *p = mp + 10 * (size_t)ch;
+                const double ex = p[1] - com[0], ey = p[2] - com[1], ez = p[3] - com[2];
+                const double Mc = p[0];
+                S[0] = S[0] + (p[4] + (Mc * ex) * ex);
+                S[1] = S[1] + (p[5] + (Mc * ey) * ey);
+                S[2] = S[2] + (p[6] + (Mc * ez) * ez);
+                S[3] = S[3] + (p[7] + (Mc * ex) * ey);
+                S[4] = S[4] + (p[8] + (Mc * ex) * ez);
+                S[5] = S[5] + (p[9] + (Mc * ey) * ez);
+            }
+        }
+        double *o = mp + 10 * (size_t)c;
+        o[0] = M;
+        o[1] = com[0];
+        o[2] = com[1];
+        o[3] = com[2];
+        for (int s = 0; s < 6; s++) o[4 + s] = S[s];
+        const double tr = (S[0] + S[1]) + S[2];
+        const double Q0 = 3.0 * S[0] - tr, Q1 = 3.0 * S[1] - tr, Q2 = 3.0 * S[2] - tr;
+        const double dx = com[0] - centre[0], dy = com[1] - centre[1], dz = com[2] - centre[2];
+        delta[c] = sqrt((dx * dx + dy * dy) + dz * dz);
+        cmac[c] = make_float4((float)com[0], (float)com[1], (float)com[2], 0.0f);
+        ceval[2 * (size_t)c] = make_float4((float)M, (float)Q0, (float)Q1, (float)Q2);
+        ceval[2 * (size_t)c + 1] =
+            make_float4((float)(3.0 * S[3]), (float)(3.0 * S[4]), (float)(3.0 * S[5]), 0.0f);
+    }
+}
+
+hipError_t launch_multipoles(const Buffers &b, hipStream_t s) {
+    const unsigned grid = min((b.cap_cells + 255u) / 256u, 2048u);
+    for (int lev = KEY_LEVELS; lev >= 0; lev--)
+        hipLaunchKernelGGL(k_multipole_level, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.topo, b.spos,
+                           b.keys[0], b.mp, b.delta, b.cmac, b.ceval, b.cap_cells);
+    return hipGetLastError();
+}
+
+// r_open = l/theta + delta with l/theta = 2^(k - level) * (1/theta) (exact
+// scaling of the host-rounded reciprocal), squared in float64, rounded once.
+__global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr,
+                                                  const uint4 *__restrict__ topo,
+                                                  const double *__restrict__ delta, double inv_theta,
+                                                  float4 *__restrict__ cmac, unsigned cap_cells) {
+#pragma clang fp contract(off)
+    if (hdr->flags & FLAG_CELLCAP) return;
+    const unsigned nc = min(hdr->ncells, cap_cells);
+    const int k = hdr->k;
+    if (blockIdx.x == 0 && threadIdx.x == 0) hdr->walk_next = 0;  // the walk that follows starts at group 0
+    for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
+        const int lev = (int)(topo[c].w >> 8);
+        const double ro = ldexp(inv_theta, k - lev) + delta[c];
+        cmac[c].w = (float)(ro * ro);
+    }
+}
+
+hipError_t launch_mac_prep(const Buffers &b, double inv_theta, hipStream_t s) {
+    const unsigned grid = min((b.cap_cells + 255u) / 256u, 4096u);
+    hipLaunchKernelGGL(k_mac_prep, dim3(grid), dim3(256), 0, s, b.hdr, b.topo, b.delta, inv_theta, b.cmac,
+                       b.cap_cells);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Energies: W = 1/2 sum m phi, T = 1/2 sum m v^2 in float64; every block sums
+// a fixed strided set, then one block sums the partials in a fixed order.
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(ENERGY_THREADS) void k_energy_partial(const float *__restrict__ mass,
+                                                                   const float *__restrict__ pot,
+                                                                   const float *__restrict__ vel,
+                                                                   unsigned n, double *__restrict__ part) {
+    double w = 0.0, t = 0.0;
+    for (unsigned i = blockIdx.x * ENERGY_THREADS + threadIdx.x; i < n; i += ENERGY_BLOCKS * ENERGY_THREADS) {
+        const double m = (double)mass[i];
+        w += m * (double)pot[i];
+        if (vel) {
+            const double vx = vel[3 * (size_t)i], vy = vel[3 * (size_t)i + 1], vz = vel[3 * (size_t)i + 2];
+            t += m * (vx * vx + vy * vy + vz * vz);
+        }
+    }
+    __shared__ double sw[ENERGY_THREADS], st[ENERGY_THREADS];
+    sw[threadIdx.x] = w;
+    st[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = ENERGY_THREADS / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
+            sw[threadIdx.x] += sw[threadIdx.x + o];
+            st[threadIdx.x] += st[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sw[0];
+        part[2 * blockIdx.x + 1] = st[0];
+    }
+}
+
+__global__ __launch_bounds__(ENERGY_THREADS) void k_energy_final(const double *__restrict__ part,
+                                                                 double *__restrict__ out) {
+    __shared__ double sw[ENERGY_THREADS], st[ENERGY_THREADS];
+    double w = 0.0, t = 0.0;
+    for (int b = threadIdx.x; b < ENERGY_BLOCKS; b += ENERGY_THREADS) {
+        w += part[2 * b];
+        t += part[2 * b + 1];
+    }
+    sw[threadIdx.x] = w;
+    st[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = ENERGY_THREADS / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
+            sw[threadIdx.x] += sw[threadIdx.x + o];
+            st[threadIdx.x] += st[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = 0.5 * st[0];
+        out[1] = 0.5 * sw[0];
+    }
+}
+
+hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
+                         unsigned n, double *d_out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_partial, dim3(ENERGY_BLOCKS), dim3(ENERGY_THREADS), 0, s, mass, pot, vel, n,
+                       b.epart);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(ENERGY_THREADS), 0, s, b.epart, d_out2);
+    return hipGetLastError();
+}
+
+}  // namespace mibh

@@ -1,0 +1,350 @@
+// Group tree walk ("tree-traverse", the >90% part of a step in the paper's
+// Results section) on gfx950.
+//
+// One wave64 per group (the vector-machine idea of Barnes 1990: one
+// interaction list shared by a group of nearby particles), persistent waves
+// pulling groups from a device-side queue.
+//
+// Traversal: lanes hold up to 64 candidate cells popped from a per-wave stack;
+// each lane applies the opening test of Barnes (1994) for the group's bounding
+// box (float32, fixed operation order); ballots + mbcnt compact accepted cells
+// into the particle-cell list, opened leaves into the particle-particle list
+// (expanded to particle indices) and opened internal cells' children onto the
+// stack.  Lanes pop in stack order and push in lane order, so stack levels
+// never decrease towards the top; then at most one step's pushes (<= 64*8)
+// per level are on the stack at any time, which bounds it by 1 + 20*512.
+//
+// Evaluation: groups average ~20 particles, so lanes run over the list
+// entries (64 sources per tile) and a wave-uniform loop runs over the group's
+// particles, 16 at a time; each lane keeps 16 x 4 partial sums, folded across
+// lanes at the end of a list by a 63-shuffle transposed reduction (lane l
+// receives the total of accumulator bitrev6(l)).  No floating-point atomics:
+// results are bitwise reproducible run to run.
+#include "mibh_device.h"
+
+namespace mibh {
+
+namespace {
+
+__device__ __forceinline__ unsigned lane64() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned rank_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ __forceinline__ unsigned uniform(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ unsigned wave_excl_scan(unsigned v, unsigned *total) {
+    unsigned x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o, 64);
+        if (lane64() >= (unsigned)o) x += y;
+    }
+    *total = uniform(__shfl(x, 63, 64));
+    return x - v;
+}
+
+__device__ __forceinline__ unsigned bitrev6(unsigned l) {
+    return ((l & 1u) << 5) | ((l & 2u) << 3) | ((l & 4u) << 1) | ((l & 8u) >> 1) | ((l & 16u) >> 3) |
+           ((l & 32u) >> 5);
+}
+
+// Sums each of the 64 per-lane values v[0..63] over the wave; lane l gets the
+// total of v[bitrev6(l)].
+__device__ __forceinline__ float transpose_reduce(float (&v)[64]) {
+    const unsigned ln = lane64();
+#pragma unroll
+    for (int s = 0; s < 6; s++) {
+        const int o = 32 >> s;
+        const int len = 64 >> s;
+        const bool hi = (ln & (unsigned)o) != 0;
+#pragma unroll
+        for (int p = 0; p < len / 2; p++) {
+            const float keep = hi ? v[2 * p + 1] : v[2 * p];
+            const float send = hi ? v[2 * p] : v[2 * p + 1];
+            v[p] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    return v[0];
+}
+
+// The opening test, float32 with every operation rounded (no contraction):
+// d_a = max(max(bmin_a - c_a, c_a - bmax_a), 0), d2 = (dx dx + dy dy) + dz dz,
+// accept iff d2 > r_open^2.
+__device__ __forceinline__ bool mac_accept(float3 bmin, float3 bmax, float4 m) {
+#pragma clang fp contract(off)
+    float u, v, t;
+    u = bmin.x - m.x; v = m.x - bmax.x; t = u > v ? u : v; const float dx = t > 0.0f ? t : 0.0f;
+    u = bmin.y - m.y; v = m.y - bmax.y; t = u > v ? u : v; const float dy = t > 0.0f ? t : 0.0f;
+    u = bmin.z - m.z; v = m.z - bmax.z; t = u > v ? u : v; const float dz = t > 0.0f ? t : 0.0f;
+    const float d2 = (dx * dx + dy * dy) + dz * dz;
+    return d2 > m.w;
+}
+
+template <bool KAHAN>
+__device__ __forceinline__ void add(float &s, float &c, float x) {
+    if (KAHAN) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += x;
+    }
+}
+
+struct WalkArgs {
+    Header *hdr;
+    const uint4 *topo;
+    const float4 *cmac;
+    const float4 *ceval;
+    const float4 *spos;
+    const uint32_t *perm;
+    const uint2 *groups;
+    uint2 *gcounts;
+    uint32_t *wstack, *wpc, *wpp;
+    float *acc, *pot;
+    float eps2, G;
+    unsigned pc_cap, pp_cap;
+};
+
+constexpr int CHUNK = 16;        // group particles per evaluation pass
+constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
+
+// Evaluates `nlist` list entries (cells if PC, particles otherwise) for all
+// `gn` group particles and adds the results into s_res (one value per lane
+// per chunk).
+template <bool KAHAN, bool PC>
+__device__ void flush(const WalkArgs &a, const uint32_t *list, unsigned nlist, unsigned gn, float px, float py,
+                      float pz, float (*s_res)[64], float (*s_cmp)[64]) {
+    __threadfence_block();
+    const unsigned ln = lane64();
+    const float eps2 = a.eps2;
+    for (unsigned c0 = 0; c0 < gn; c0 += CHUNK) {
+        const unsigned cn = min((unsigned)CHUNK, gn - c0);
+        float xi[CHUNK], yi[CHUNK], zi[CHUNK];
+#pragma unroll
+        for (int ii = 0; ii < CHUNK; ii++) {
+            const unsigned src = c0 + min((unsigned)ii, cn - 1);
+            xi[ii] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(px), src));
+            yi[ii] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(py), src));
+            zi[ii] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pz), src));
+        }
+        float v[64], cv[64];
+#pragma unroll
+        for (int j = 0; j < 64; j++) { v[j] = 0.0f; cv[j] = 0.0f; }
+        for (unsigned t0 = 0; t0 < nlist; t0 += 64) {
+            const unsigned k = t0 + ln;
+            const bool valid = k < nlist;
+            const unsigned e = valid ? list[k] : 0u;
+            if (PC) {
+                float4 m = a.cmac[e], q0 = a.ceval[2 * (size_t)e], q1 = a.ceval[2 * (size_t)e + 1];
+                if (!valid) {
+                    m = make_float4(FAR, FAR, FAR, 0.0f);
+                    q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    q1 = q0;
+                }
+#pragma unroll
+                for (int ii = 0; ii < CHUNK; ii++) {
+                    if ((unsigned)ii < cn) {
+                        // R = x - com; r2 = R.R + eps2
+                        const float Rx = xi[ii] - m.x, Ry = yi[ii] - m.y, Rz = zi[ii] - m.z;
+                        const float r2 = fmaf(Rz, Rz, fmaf(Ry, Ry, fmaf(Rx, Rx, eps2)));
+                        const float rinv = __builtin_amdgcn_rsqf(r2);
+                        const float rinv2 = rinv * rinv;
+                        const float r3 = rinv * rinv2;
+                        const float r5 = r3 * rinv2;
+                        // Q R with Q = (xx, yy, zz | xy, xz, yz)
+                        const float QRx = fmaf(q0.y, Rx, fmaf(q1.x, Ry, q1.y * Rz));
+                        const float QRy = fmaf(q1.x, Rx, fmaf(q0.z, Ry, q1.z * Rz));
+                        const float QRz = fmaf(q1.y, Rx, fmaf(q1.z, Ry, q0.w * Rz));
+                        const float RQR = fmaf(Rx, QRx, fmaf(Ry, QRy, Rz * QRz));
+                        const float Mr3 = q0.x * r3;
+                        const float u = RQR * r5;
+                        // a = -M R/r^3 + Q R/r^5 - (5/2)(RQR) R/r^7 ; phi = -(M/r + RQR/(2 r^5))
+                        const float coef = fmaf(2.5f * u, rinv2, Mr3);
+                        add<KAHAN>(v[4 * ii + 0], cv[4 * ii + 0], fmaf(QRx, r5, -coef * Rx));
+                        add<KAHAN>(v[4 * ii + 1], cv[4 * ii + 1], fmaf(QRy, r5, -coef * Ry));
+                        add<KAHAN>(v[4 * ii + 2], cv[4 * ii + 2], fmaf(QRz, r5, -coef * Rz));
+                        add<KAHAN>(v[4 * ii + 3], cv[4 * ii + 3], -fmaf(0.5f, u, q0.x * rinv));
+                    }
+                }
+            } else {
+                float4 s = a.spos[e];
+                if (!valid) s = make_float4(FAR, FAR, FAR, 0.0f);
+#pragma unroll
+                for (int ii = 0; ii < CHUNK; ii++) {
+                    if ((unsigned)ii < cn) {
+                        const float dx = s.x - xi[ii], dy = s.y - yi[ii], dz = s.z - zi[ii];
+                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        float rinv = __builtin_amdgcn_rsqf(r2 + eps2);
+                        rinv = r2 > 0.0f ? rinv : 0.0f;  // self and coincident pairs contribute nothing
+                        const float mr = s.w * rinv;
+                        const float mr3 = mr * rinv * rinv;
+                        add<KAHAN>(v[4 * ii + 0], cv[4 * ii + 0], mr3 * dx);
+                        add<KAHAN>(v[4 * ii + 1], cv[4 * ii + 1], mr3 * dy);
+                        add<KAHAN>(v[4 * ii + 2], cv[4 * ii + 2], mr3 * dz);
+                        add<KAHAN>(v[4 * ii + 3], cv[4 * ii + 3], -mr);
+                    }
+                }
+            }
+        }
+        if (KAHAN) {
+#pragma unroll
+            for (int j = 0; j < 64; j++) v[j] = v[j] - cv[j];
+        }
+        const float r = transpose_reduce(v);
+        add<KAHAN>(s_res[c0 / CHUNK][ln], s_cmp[c0 / CHUNK][ln], r);
+    }
+}
+
+template <bool KAHAN>
+__global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
+    __shared__ float s_res[4][64];
+    __shared__ float s_cmp[4][64];
+    const unsigned ln = lane64();
+    const unsigned slot = blockIdx.x;
+    uint32_t *stk = a.wstack + (size_t)slot * STACK_CAP;
+    uint32_t *pcl = a.wpc + (size_t)slot * a.pc_cap;
+    uint32_t *ppl = a.wpp + (size_t)slot * a.pp_cap;
+    if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
+    const unsigned ngroups = a.hdr->ngroups;
+    const unsigned rounds_cap = a.pp_cap >> 6;  // particles a lane may add per round
+    for (;;) {
+        unsigned g = 0;
+        if (ln == 0) g = atomicAdd(&a.hdr->walk_next, 1u);
+        g = uniform(__shfl(g, 0, 64));
+        if (g >= ngroups) break;
+        const uint2 gr = a.groups[g];
+        const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform(gr.y >> 8);
+        const float4 p = a.spos[gf + min(ln, gn - 1)];
+        float3 bmin = make_float3(p.x, p.y, p.z), bmax = bmin;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            bmin.x = fminf(bmin.x, __shfl_xor(bmin.x, o, 64));
+            bmin.y = fminf(bmin.y, __shfl_xor(bmin.y, o, 64));
+            bmin.z = fminf(bmin.z, __shfl_xor(bmin.z, o, 64));
+            bmax.x = fmaxf(bmax.x, __shfl_xor(bmax.x, o, 64));
+            bmax.y = fmaxf(bmax.y, __shfl_xor(bmax.y, o, 64));
+            bmax.z = fmaxf(bmax.z, __shfl_xor(bmax.z, o, 64));
+        }
+#pragma unroll
+        for (int c = 0; c < 4; c++) { s_res[c][ln] = 0.0f; s_cmp[c][ln] = 0.0f; }
+
+        unsigned top = 1, npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
+        bool overflow = false;
+        if (ln == 0) stk[0] = 0u;
+        __threadfence_block();
+        while (top > 0) {
+            const unsigned m = min(top, 64u);
+            const unsigned base = top - m;
+            const bool valid = ln < m;
+            const unsigned c = valid ? stk[base + ln] : 0u;
+            top = base;
+            const uint4 t = a.topo[c];
+            const float4 mc = a.cmac[c];
+            const unsigned lvl = t.w >> 8, nch = t.w & 255u;
+            const bool anc = t.x <= gf && gf < t.x + t.y && lvl <= glev;
+            const bool accept = valid && !anc && mac_accept(bmin, bmax, mc);
+            const bool opened = valid && !accept;
+            const bool leaf = opened && nch == 0;
+            const bool push = opened && nch != 0;
+
+            // accepted cells -> particle-cell list
+            const unsigned long long am = __ballot(accept);
+            const unsigned na = (unsigned)__popcll(am);
+            if (npc + na > a.pc_cap) {
+                flush<KAHAN, true>(a, pcl, npc, gn, p.x, p.y, p.z, s_res, s_cmp);
+                npc = 0;
+            }
+            if (accept) pcl[npc + rank_below(am)] = c;
+            npc += na;
+            tot_pc += na;
+
+            // opened leaves -> particle-particle list, in rounds bounded by the capacity
+            unsigned rem = leaf ? t.y : 0u, src = t.x;
+            while (__ballot(rem > 0)) {
+                const unsigned take = min(rem, rounds_cap);
+                unsigned sum;
+                const unsigned off = wave_excl_scan(take, &sum);
+                if (npp + sum > a.pp_cap) {
+                    flush<KAHAN, false>(a, ppl, npp, gn, p.x, p.y, p.z, s_res, s_cmp);
+                    npp = 0;
+                }
+                for (unsigned j = 0; j < take; j++) ppl[npp + off + j] = src + j;
+                npp += sum;
+                tot_pp += sum;
+                rem -= take;
+                src += take;
+            }
+
+            // opened internal cells -> children onto the stack
+            unsigned nsum;
+            const unsigned nc = push ? nch : 0u;
+            const unsigned off = wave_excl_scan(nc, &nsum);
+            if (top + nsum > STACK_CAP) {
+                overflow = true;
+                break;
+            }
+            for (unsigned j = 0; j < nc; j++) stk[top + off + j] = t.z + j;
+            top += nsum;
+            __threadfence_block();
+        }
+        if (overflow) {
+            if (ln == 0) atomicOr(&a.hdr->flags, FLAG_STACK);
+            continue;
+        }
+        if (npc) flush<KAHAN, true>(a, pcl, npc, gn, p.x, p.y, p.z, s_res, s_cmp);
+        if (npp) flush<KAHAN, false>(a, ppl, npp, gn, p.x, p.y, p.z, s_res, s_cmp);
+
+        // results back to the caller's order
+        const unsigned idx = bitrev6(ln);
+        const unsigned comp = idx & 3u;
+        for (unsigned c = 0; c * CHUNK < gn; c++) {
+            const unsigned pi = c * CHUNK + (idx >> 2);
+            if (pi < gn) {
+                float val = s_res[c][ln];
+                if (KAHAN) val = val - s_cmp[c][ln];
+                val *= a.G;
+                const size_t orig = a.perm[gf + pi];
+                if (comp < 3) a.acc[3 * orig + comp] = val;
+                else a.pot[orig] = val;
+            }
+        }
+        if (ln == 0) a.gcounts[g] = make_uint2(tot_pc, tot_pp);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_walk(const Buffers &b, unsigned n, float eps2, float G, int precision, float *acc,
+                       float *pot, hipStream_t s) {
+    (void)n;
+    WalkArgs a;
+    a.hdr = b.hdr;
+    a.topo = b.topo;
+    a.cmac = b.cmac;
+    a.ceval = b.ceval;
+    a.spos = b.spos;
+    a.perm = b.vals[0];
+    a.groups = b.groups;
+    a.gcounts = b.gcounts;
+    a.wstack = b.wstack;
+    a.wpc = b.wpc;
+    a.wpp = b.wpp;
+    a.acc = acc;
+    a.pot = pot;
+    a.eps2 = eps2;
+    a.G = G;
+    a.pc_cap = b.pc_cap;
+    a.pp_cap = b.pp_cap;
+    if (precision == 1)
+        hipLaunchKernelGGL(k_walk<true>, dim3(b.walk_waves), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_walk<false>, dim3(b.walk_waves), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mibh

@@ -1,0 +1,256 @@
+"""Thin ctypes binding of libmibh.so (include/mibh.h).
+
+Argument marshalling only: every step of the force computation runs in the
+library's HIP kernels.  PyTorch provides device memory (the workspace and the
+caller's tensors) and the stream.  The functions keep the C names without the
+``mibh_`` prefix; ``Context`` bundles a context handle with its workspace.
+
+Importing this module does not touch the GPU; loading the library happens on
+first use and raises ImportError when libmibh.so has not been built (there is
+no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmibh.so")
+
+PLAIN, KAHAN = 0, 1
+EXPORTS = {
+    "keys": 0, "perm": 1, "cells": 2, "groups": 3, "counts": 4, "multipoles": 5, "delta": 6,
+    "mac": 7, "quad": 8, "spos": 9,
+}
+STAGES = ("sorting", "moving", "tree_construction", "multipoles", "mac_prep", "walk")
+STATUS = {0: "MIBH_OK", -1: "MIBH_EINVAL", -2: "MIBH_ENOMEM", -3: "MIBH_EHIP", -4: "MIBH_ESTATE",
+          -5: "MIBH_EOVERFLOW", -6: "MIBH_ENONFINITE"}
+
+
+class MibhError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("ncrit", C.c_int32), ("group_cap", C.c_int32), ("eps2", C.c_float), ("G", C.c_float),
+                ("precision", C.c_int32), ("walk_waves", C.c_int32), ("pc_cap", C.c_int32),
+                ("pp_cap", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ncells", C.c_int64), ("ngroups", C.c_int64), ("nleaves", C.c_int64),
+                ("depth", C.c_int32), ("root_k", C.c_int32), ("sum_pc", C.c_uint64),
+                ("sum_pp", C.c_uint64), ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; ImportError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1204_2280_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i64, st = C.c_void_p, C.c_int64, C.c_int
+        L.mibh_default_params.argtypes = [C.POINTER(Params)]
+        L.mibh_default_params.restype = None
+        L.mibh_workspace_bytes.argtypes = [i64, C.POINTER(Params)]
+        L.mibh_workspace_bytes.restype = C.c_size_t
+        L.mibh_create.argtypes = [C.POINTER(Params), i64, P, C.c_size_t, P, C.POINTER(P)]
+        L.mibh_destroy.argtypes = [P]
+        L.mibh_build_tree.argtypes = [P, P, P, i64]
+        L.mibh_compute_multipoles.argtypes = [P]
+        L.mibh_compute_forces.argtypes = [P, C.c_float, P, P]
+        L.mibh_forces.argtypes = [P, P, P, i64, C.c_float, P, P]
+        L.mibh_sync.argtypes = [P]
+        L.mibh_stats.argtypes = [P, C.POINTER(Stats)]
+        L.mibh_energy.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.mibh_export_bytes.argtypes = [P, C.c_int, C.POINTER(C.c_size_t)]
+        L.mibh_export.argtypes = [P, C.c_int, P, C.c_size_t]
+        for f in ("mibh_create", "mibh_destroy", "mibh_build_tree", "mibh_compute_multipoles",
+                  "mibh_compute_forces", "mibh_forces", "mibh_sync", "mibh_stats", "mibh_energy",
+                  "mibh_export_bytes", "mibh_export"):
+            getattr(L, f).restype = st
+        L.mibh_profile_begin.argtypes = [P, C.c_int]
+        L.mibh_profile_read.argtypes = [P, P, C.c_int, C.POINTER(C.c_int)]
+        L.mibh_profile_begin.restype = st
+        L.mibh_profile_read.restype = st
+        L.mibh_status_string.argtypes = [st]
+        L.mibh_status_string.restype = C.c_char_p
+        L.mibh_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise MibhError(status, lib().mibh_last_error().decode(errors="replace"))
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().mibh_default_params(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(n_max: int, params: Params | None = None) -> int:
+    return int(lib().mibh_workspace_bytes(n_max, None if params is None else C.byref(params)))
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else None
+
+
+def _require(t, dtype, shape_tail, device, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+
+
+class Context:
+    """A library context with its workspace (a torch uint8 tensor) and stream."""
+
+    def __init__(self, n_max: int, params: Params | None = None, device=None, stream=None, **overrides):
+        import torch
+        dev = torch.device(device if device is not None else "cuda")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.params = params if params is not None else default_params(**overrides)
+        nbytes = workspace_bytes(n_max, self.params)
+        if nbytes == 0:
+            raise MibhError(-1, "invalid n_max or parameters")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            h = C.c_void_p()
+            _check(lib().mibh_create(C.byref(self.params), n_max, aligned, nbytes, self.stream.cuda_stream,
+                                     C.byref(h)))
+        self.handle = h
+        self.n_max = n_max
+        self.n = 0
+        self._keep = ()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mibh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- the C entry points -------------------------------------------------
+    def build_tree(self, pos, mass):
+        import torch
+        n = int(mass.shape[0]) if mass.dim() == 1 else -1
+        _require(pos, torch.float32, (3,), self.device, "pos")
+        _require(mass, torch.float32, (), self.device, "mass")
+        if pos.shape[0] != n:
+            raise ValueError("pos and mass sizes differ")
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_build_tree(self.handle, pos.data_ptr(), mass.data_ptr(), n))
+        self.n = n
+        self._keep = (pos, mass)
+
+    def compute_multipoles(self):
+        _check(lib().mibh_compute_multipoles(self.handle))
+
+    def compute_forces(self, theta: float, acc=None, pot=None):
+        import torch
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
+        if pot is None:
+            pot = torch.empty((self.n,), dtype=torch.float32, device=self.device)
+        _require(acc, torch.float32, (3,), self.device, "acc")
+        _require(pot, torch.float32, (), self.device, "pot")
+        if acc.shape[0] != self.n or pot.shape[0] != self.n:
+            raise ValueError("output sizes differ from the tree's particle count")
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_compute_forces(self.handle, float(theta), acc.data_ptr(), pot.data_ptr()))
+        self._out = (acc, pot)
+        return acc, pot
+
+    def forces(self, pos, mass, theta: float, acc=None, pot=None):
+        self.build_tree(pos, mass)
+        self.compute_multipoles()
+        return self.compute_forces(theta, acc, pot)
+
+    def sync(self):
+        _check(lib().mibh_sync(self.handle))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().mibh_stats(self.handle, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def energy(self, vel=None):
+        T, W = C.c_double(), C.c_double()
+        _check(lib().mibh_energy(self.handle, _ptr(vel), C.byref(T), C.byref(W)))
+        return T.value, W.value
+
+    def profile_begin(self, max_steps: int):
+        """Record stage events for the next max_steps steps."""
+        _check(lib().mibh_profile_begin(self.handle, max_steps))
+        self._prof_max = max_steps
+
+    def profile_read(self):
+        """Per-step stage times in ms: list of dicts keyed by STAGES (synchronises)."""
+        import numpy as np
+        ms = np.zeros((self._prof_max, len(STAGES)), dtype=np.float32)
+        ns = C.c_int()
+        _check(lib().mibh_profile_read(self.handle, ms.ctypes.data, self._prof_max, C.byref(ns)))
+        return [dict(zip(STAGES, map(float, ms[k]))) for k in range(ns.value)]
+
+    def export(self, what: str):
+        """Copy of an internal array as a torch tensor on the device."""
+        import torch
+        code = EXPORTS[what]
+        nb = C.c_size_t()
+        _check(lib().mibh_export_bytes(self.handle, code, C.byref(nb)))
+        buf = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=self.device)
+        _check(lib().mibh_export(self.handle, code, buf.data_ptr(), buf.numel()))
+        buf = buf[:nb.value]
+        view = {"keys": (torch.int64, (-1,)), "perm": (torch.int32, (-1,)), "cells": (torch.int32, (-1, 4)),
+                "groups": (torch.int32, (-1, 2)), "counts": (torch.int32, (-1, 2)),
+                "multipoles": (torch.float64, (-1, 10)), "delta": (torch.float64, (-1,)),
+                "mac": (torch.float32, (-1, 4)), "quad": (torch.float32, (-1, 8)),
+                "spos": (torch.float32, (-1, 4))}[what]
+        return buf.view(view[0]).reshape(view[1])
+
+
+@dataclass
+class Decoded:
+    """Host-side numpy views of exported integer arrays, decoded to the oracle's fields."""
+
+    @staticmethod
+    def cells(t):
+        import numpy as np
+        a = t.cpu().numpy().view(np.uint32).reshape(-1, 4)
+        return {"first": a[:, 0].astype(np.int64), "count": a[:, 1].astype(np.int64),
+                "child_first": a[:, 2].astype(np.int64), "level": (a[:, 3] >> 8).astype(np.int32),
+                "nchild": (a[:, 3] & 255).astype(np.int32)}
+
+    @staticmethod
+    def groups(t):
+        import numpy as np
+        a = t.cpu().numpy().view(np.uint32).reshape(-1, 2)
+        return {"first": a[:, 0].astype(np.int64), "count": (a[:, 1] & 255).astype(np.int64),
+                "level": (a[:, 1] >> 8).astype(np.int32)}

@@ -1,0 +1,216 @@
+"""GPU parity of the whole force step against the float64 oracle.
+
+Integer and index artefacts (keys, permutation, cells, groups, interaction
+counts) and the float64 multipoles / float32 MAC data must match bit for bit;
+accelerations and potentials within 1e-5 relative error at the 99th
+percentile.  Every case calls the HIP library through its C ABI.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import (TOL_P99, assert_multipoles_equal, assert_tree_equal, gpu_context, p99, rel_err,
+                         run_gpu)
+from paper_1204_2280_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name == "plummer_32k":
+        p, _, m = W.plummer(32768, 1, with_velocities=False)
+    elif name == "plummer_5003":  # ragged tail for every tile size
+        p, _, m = W.plummer(5003, 11, with_velocities=False)
+    elif name == "hernquist_9000":
+        p, m = W.hernquist(9000, 12)
+    elif name == "cube_4097":
+        p, m = W.uniform_cube(4097, 13)
+    elif name == "coincident_300":
+        p = np.tile(np.array([[0.25, -0.5, 0.125]], np.float32), (300, 1))
+        p = np.concatenate([p, W.uniform_cube(50, 3)[0]])
+        m = np.full(350, 1 / 350, np.float32)
+    elif name == "line_2000":
+        p = np.zeros((2000, 3), np.float32)
+        p[:, 1] = np.linspace(-3, 5, 2000, dtype=np.float32)
+        m = np.full(2000, 1 / 2000, np.float32)
+    elif name == "unequal_mass_6000":
+        p, _, m = W.plummer(6000, 14, with_velocities=False)
+        m = (m * np.linspace(0.1, 1.9, 6000)).astype(np.float32)
+    elif name.startswith("tiny_"):
+        n = int(name.split("_")[1])
+        p, _, m = W.plummer(n, 100 + n, with_velocities=False)
+    else:
+        raise KeyError(name)
+    return np.ascontiguousarray(p, np.float32), np.ascontiguousarray(m, np.float32)
+
+
+CASES = ["plummer_32k", "plummer_5003", "hernquist_9000", "cube_4097", "coincident_300", "line_2000",
+         "unequal_mass_6000", "tiny_1", "tiny_2", "tiny_17", "tiny_65", "tiny_300"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_context(40000)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_step_matches_oracle(ctx, orc, name):
+    pos, mass = _case(name)
+    theta = 0.75
+    print(f"[gpu] case {name} n={len(mass)} theta={theta}", flush=True)
+    g = run_gpu(ctx, pos, mass, theta)
+    T = orc.Tree(pos, mass)
+    T.walk(theta)
+    assert_tree_equal(g, T)
+    np.testing.assert_array_equal(g["spos"][:, :3], pos[T.perm])
+    np.testing.assert_array_equal(g["spos"][:, 3], mass[T.perm])
+    assert_multipoles_equal(g, T, theta)
+    npc, npp = T.counts()
+    np.testing.assert_array_equal(g["counts"][:, 0], npc)
+    np.testing.assert_array_equal(g["counts"][:, 1], npp)
+    acc, pot = T.forces()
+    if len(mass) == 1:
+        assert np.all(g["acc"] == 0) and np.all(g["pot"] == 0)
+        return
+    ea, ep = rel_err(g["acc"], acc), rel_err(g["pot"], pot)
+    print(f"[gpu] {name}: acc p99 {p99(ea):.2e} max {ea.max():.2e}; pot p99 {p99(ep):.2e}", flush=True)
+    assert p99(ea) <= TOL_P99 and p99(ep) <= TOL_P99
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0, 1e-4, 2.0])
+def test_theta_sweep(ctx, orc, theta):
+    pos, mass = _case("plummer_5003")
+    print(f"[gpu] theta sweep {theta}", flush=True)
+    g = run_gpu(ctx, pos, mass, theta, exports=("counts", "mac"))
+    T = orc.Tree(pos, mass)
+    T.walk(theta)
+    mac = T.mac_prep(theta)
+    np.testing.assert_array_equal(g["mac"][:, 3], mac["r2open"])
+    npc, npp = T.counts()
+    np.testing.assert_array_equal(g["counts"][:, 0], npc)
+    np.testing.assert_array_equal(g["counts"][:, 1], npp)
+    acc, pot = T.forces()
+    assert p99(rel_err(g["acc"], acc)) <= TOL_P99 and p99(rel_err(g["pot"], pot)) <= TOL_P99
+
+
+def test_repeated_walks_and_determinism(ctx, orc):
+    import torch
+    pos, mass = _case("plummer_32k")
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    a1, p1 = [t.clone() for t in ctx.forces(p, m, 0.75)]
+    ctx.compute_forces(0.5)
+    a2, p2 = ctx.compute_forces(0.75)
+    ctx.sync()
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+    a3, p3 = ctx.forces(p, m, 0.75)
+    ctx.sync()
+    assert torch.equal(a1, a3) and torch.equal(p1, p3)
+
+
+def test_small_list_capacities_force_flushes(orc):
+    """Tiny per-wave list capacities exercise the mid-traversal evaluation flushes."""
+    pos, mass = _case("plummer_5003")
+    c = gpu_context(6000, pc_cap=64, pp_cap=64, walk_waves=37)
+    g = run_gpu(c, pos, mass, 0.75, exports=("counts",))
+    T = orc.Tree(pos, mass)
+    T.walk(0.75)
+    npc, npp = T.counts()
+    np.testing.assert_array_equal(g["counts"][:, 0], npc)
+    np.testing.assert_array_equal(g["counts"][:, 1], npp)
+    acc, pot = T.forces()
+    assert p99(rel_err(g["acc"], acc)) <= TOL_P99 and p99(rel_err(g["pot"], pot)) <= TOL_P99
+
+
+@pytest.mark.parametrize("ncrit,gcap", [(8, 32), (1, 1), (32, 64), (16, 16)])
+def test_other_leaf_and_group_sizes(orc, ncrit, gcap):
+    pos, mass = _case("hernquist_9000")
+    c = gpu_context(9000, ncrit=ncrit, group_cap=gcap)
+    g = run_gpu(c, pos, mass, 0.75)
+    T = orc.Tree(pos, mass, ncrit=ncrit, gcap=gcap)
+    T.walk(0.75)
+    assert_tree_equal(g, T)
+    assert_multipoles_equal(g, T, 0.75)
+    npc, npp = T.counts()
+    np.testing.assert_array_equal(g["counts"][:, 0], npc)
+    np.testing.assert_array_equal(g["counts"][:, 1], npp)
+    acc, pot = T.forces()
+    assert p99(rel_err(g["acc"], acc)) <= TOL_P99
+
+
+def test_softening_and_G(orc):
+    pos, mass = _case("plummer_5003")
+    c = gpu_context(6000, eps2=1e-4, G=2.5)
+    g = run_gpu(c, pos, mass, 0.75, exports=("counts",))
+    T = orc.Tree(pos, mass)
+    T.walk(0.75, eps2=float(np.float32(1e-4)), G=2.5)
+    acc, pot = T.forces()
+    assert p99(rel_err(g["acc"], acc)) <= TOL_P99 and p99(rel_err(g["pot"], pot)) <= TOL_P99
+
+
+def test_kahan_matches_and_is_not_worse(orc):
+    pos, mass = _case("plummer_32k")
+    T = orc.Tree(pos, mass)
+    T.walk(0.75)
+    acc, pot = T.forces()
+    errs = {}
+    for prec in (0, 1):
+        c = gpu_context(33000, precision=prec)
+        g = run_gpu(c, pos, mass, 0.75, exports=("counts",))
+        npc, npp = T.counts()
+        np.testing.assert_array_equal(g["counts"][:, 0], npc)
+        e = rel_err(g["acc"], acc)
+        errs[prec] = (p99(e), float(np.sqrt(np.mean(e ** 2))))
+        assert p99(e) <= TOL_P99
+    print(f"[gpu] plain p99/rms {errs[0]}, kahan {errs[1]}", flush=True)
+    assert errs[1][0] <= errs[0][0] * 1.05
+
+
+def test_energy_float64(ctx, orc):
+    import torch
+    pos, vel, mass = W.plummer(32768, 1)
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    v = torch.from_numpy(vel).to(ctx.device)
+    acc, pot = ctx.forces(p, m, 0.75)
+    T, Wp = ctx.energy(v)
+    To, Wo = orc.energy(mass, pot.cpu().numpy().astype(np.float64), vel)
+    assert abs(T - To) <= 1e-12 * abs(To) and abs(Wp - Wo) <= 1e-12 * abs(Wo)
+    assert abs(Wp + 0.5) < 3 / np.sqrt(32768) and abs(T + Wp + 0.25) < 3 / np.sqrt(32768)
+
+
+def test_error_paths(ctx):
+    import torch
+    from paper_1204_2280_amd import mibh
+    pos, mass = _case("tiny_300")
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    c = gpu_context(300)
+    with pytest.raises(mibh.MibhError) as e:
+        c.compute_forces(0.75)
+    assert e.value.status == -4
+    c.forces(p, m, 0.75)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(mibh.MibhError) as e:
+            c.compute_forces(bad)
+        assert e.value.status == -1
+    big = torch.zeros((301, 3), dtype=torch.float32, device=ctx.device)
+    with pytest.raises(mibh.MibhError) as e:
+        c.build_tree(big, torch.ones(301, dtype=torch.float32, device=ctx.device))
+    assert e.value.status == -1
+    bad = p.clone()
+    bad[7, 1] = float("nan")
+    c.forces(bad, m, 0.75)
+    with pytest.raises(mibh.MibhError) as e:
+        c.sync()
+    assert e.value.status == -6
+    negm = m.clone()
+    negm[3] = -1.0
+    c.forces(p, negm, 0.75)
+    with pytest.raises(mibh.MibhError) as e:
+        c.sync()
+    assert e.value.status == -6
+    # a clean step afterwards works again
+    c.forces(p, m, 0.75)
+    c.sync()
+    with pytest.raises(mibh.MibhError):
+        gpu_context(10, ncrit=65, group_cap=64)

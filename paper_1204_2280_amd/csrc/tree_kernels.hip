@@ -277,6 +277,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__r
     for (unsigned j = threadIdx.x; j < (SORT_THREADS / 64) * RADIX; j += SORT_THREADS) (&h[0][0])[j] = 0;
     __syncthreads();
     const unsigned base = blockIdx.x * SORT_TILE + w * (64 * SORT_ITEMS);
+#pragma unroll
     for (int t = 0; t < SORT_ITEMS; t++) {
         const unsigned idx = base + t * 64 + ln;
         const bool valid = idx < n;
@@ -482,14 +483,19 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_count(
     }
     if (valid) lvinfo[i] = make_uchar4((unsigned char)clo, (unsigned char)leaf, (unsigned char)glev,
                                        (unsigned char)((gstart ? 1 : 0) | (oversized << 1)));
+    // Padding threads start no cell (first level 1 > leaf level 0) and no
+    // group, so the ballot loops below need no per-lane validity branch; the
+    // wave-uniform counts are stored by every lane.
+    const int c_lo = valid ? clo : 1, c_hi = valid ? leaf : 0;
+    const bool g_st = valid && gstart;
     const unsigned w = threadIdx.x >> 6;
     for (int l = 0; l <= KEY_LEVELS; l++) {
-        const unsigned long long b = __ballot(valid && clo <= l && l <= leaf);
-        if (lane64() == 0) s_cnt[w][l] = (uint32_t)__popcll(b);
+        const unsigned long long b = __ballot(c_lo <= l && l <= c_hi);
+        s_cnt[w][l] = (uint32_t)__popcll(b);
     }
     {
-        const unsigned long long b = __ballot(valid && gstart);
-        if (lane64() == 0) s_cnt[w][NCOUNTERS - 1] = (uint32_t)__popcll(b);
+        const unsigned long long b = __ballot(g_st);
+        s_cnt[w][NCOUNTERS - 1] = (uint32_t)__popcll(b);
     }
     __syncthreads();
     if (threadIdx.x < NCOUNTERS) {
@@ -545,14 +551,15 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
     if (threadIdx.x < NCOUNTERS) s_blk[threadIdx.x] = blkcnt[(size_t)threadIdx.x * nblk + blockIdx.x];
     const unsigned i = blockIdx.x * BUILD_THREADS + threadIdx.x;
     const bool valid = i < n;
+    // padding threads: first level 1 > leaf level 0 and no group start
     const uchar4 info = valid ? lvinfo[i] : make_uchar4(1, 0, 0, 0);
     const int clo = info.x, leaf = info.y, glev = info.z;
-    const bool gstart = valid && (info.w & 1);
+    const bool gstart = (info.w & 1) != 0;
     const unsigned w = threadIdx.x >> 6;
     for (int c = 0; c < NCOUNTERS; c++) {
-        const bool pred = c < NCOUNTERS - 1 ? (valid && clo <= c && c <= leaf) : gstart;
+        const bool pred = c < NCOUNTERS - 1 ? (clo <= c && c <= leaf) : gstart;
         const unsigned long long b = __ballot(pred);
-        if (lane64() == 0) s_wpre[w][c] = (uint32_t)__popcll(b);
+        s_wpre[w][c] = (uint32_t)__popcll(b);
     }
     __syncthreads();
     if (threadIdx.x < NCOUNTERS) {
@@ -567,7 +574,7 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
     // cells, deepest level first so that each cell knows its first child's number
     unsigned next = 0;
     for (int l = KEY_LEVELS; l >= 0; l--) {
-        const bool pred = valid && clo <= l && l <= leaf;
+        const bool pred = clo <= l && l <= leaf;
         const unsigned long long b = __ballot(pred);
         if (pred) {
             const unsigned idx = s_base[l] + s_blk[l] + s_wpre[w][l] + rank_below(b);

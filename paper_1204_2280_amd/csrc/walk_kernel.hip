@@ -213,9 +213,11 @@ __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
     const unsigned ngroups = a.hdr->ngroups;
     const unsigned rounds_cap = a.pp_cap >> 6;  // particles a lane may add per round
     for (;;) {
-        unsigned g = 0;
-        if (ln == 0) g = atomicAdd(&a.hdr->walk_next, 1u);
-        g = uniform(__shfl(g, 0, 64));
+        // Every lane executes the queue atomic (only lane 0 adds 1) so that no
+        // lane-dependent branch sits inside this loop: the compiler may split a
+        // loop on a loop-invariant divergent condition, which would separate
+        // lane 0 from the cross-lane operations of the other lanes.
+        const unsigned g = uniform(atomicAdd(&a.hdr->walk_next, ln == 0 ? 1u : 0u));
         if (g >= ngroups) break;
         const uint2 gr = a.groups[g];
         const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform(gr.y >> 8);
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
 
         unsigned top = 1, npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
         bool overflow = false;
-        if (ln == 0) stk[0] = 0u;
+        stk[0] = 0u;  // the root (all lanes store the same value)
         __threadfence_block();
         while (top > 0) {
             const unsigned m = min(top, 64u);
@@ -293,7 +295,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
             __threadfence_block();
         }
         if (overflow) {
-            if (ln == 0) atomicOr(&a.hdr->flags, FLAG_STACK);
+            atomicOr(&a.hdr->flags, FLAG_STACK);
             continue;
         }
         if (npc) flush<KAHAN, true>(a, pcl, npc, gn, p.x, p.y, p.z, s_res, s_cmp);
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
                 else a.pot[orig] = val;
             }
         }
-        if (ln == 0) a.gcounts[g] = make_uint2(tot_pc, tot_pp);
+        a.gcounts[g] = make_uint2(tot_pc, tot_pp);  // same value from every lane
     }
 }
 

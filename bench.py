@@ -57,7 +57,7 @@ def measured_traffic(workload: str):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 16):
+def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 2):
     """The float64 oracle on the host cores: full tree build on all particles
     plus the walk of a sample of groups, the walk time scaled to all groups."""
     import numpy as np
@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--walk-waves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-check-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the force step is single-GPU); --gpus {args.gpus} "
@@ -193,6 +195,14 @@ def main():
             "walk_ms": walk_ms,
         },
     }
+    if args.copy_check_mib > 0:
+        nb = args.copy_check_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_check_bytes"] = nb
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(pos, mass, theta)

@@ -54,6 +54,23 @@ def rel_err(a, ref):
     return num / np.where(den > 0, den, 1.0)
 
 
+def term_scale(pos, mass, G=1.0):
+    """S_i = sum_j G m_j / r_ij^2: the summed magnitude of particle i's direct
+    terms.  float32 evaluation of a sum with condition S_i/|a_i| can only be
+    expected to reach |error| ~ u * S_i, so ill-conditioned edge cases (points
+    on a line, coincident clumps) are checked with |error| / S_i."""
+    x = np.asarray(pos, np.float64)
+    m = np.asarray(mass, np.float64)
+    S = np.zeros(len(m))
+    for b in range(0, len(m), 512):
+        d = x[None, :, :] - x[b:b + 512, None, :]
+        r2 = np.sum(d * d, axis=2)
+        with np.errstate(divide="ignore"):
+            w = np.where(r2 > 0, m[None, :] / r2, 0.0)
+        S[b:b + 512] = G * w.sum(axis=1)
+    return S
+
+
 def p99(e):
     e = np.sort(np.asarray(e))
     if e.size == 0:

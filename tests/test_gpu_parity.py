@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from gpu_helpers import (TOL_P99, assert_multipoles_equal, assert_tree_equal, gpu_context, p99, rel_err,
-                         run_gpu)
+                         run_gpu, term_scale)
 from paper_1204_2280_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -43,6 +43,9 @@ def _case(name):
     return np.ascontiguousarray(p, np.float32), np.ascontiguousarray(m, np.float32)
 
 
+# inputs whose net forces cancel to a tiny fraction of the individual terms
+ILL_CONDITIONED = {"line_2000", "coincident_300"}
+
 CASES = ["plummer_32k", "plummer_5003", "hernquist_9000", "cube_4097", "coincident_300", "line_2000",
          "unequal_mass_6000", "tiny_1", "tiny_2", "tiny_17", "tiny_65", "tiny_300"]
 
@@ -73,7 +76,12 @@ def test_step_matches_oracle(ctx, orc, name):
         return
     ea, ep = rel_err(g["acc"], acc), rel_err(g["pot"], pot)
     print(f"[gpu] {name}: acc p99 {p99(ea):.2e} max {ea.max():.2e}; pot p99 {p99(ep):.2e}", flush=True)
-    assert p99(ea) <= TOL_P99 and p99(ep) <= TOL_P99
+    if name in ILL_CONDITIONED:
+        ec = np.linalg.norm(g["acc"] - acc, axis=1) / term_scale(pos, mass)
+        print(f"[gpu] {name}: |acc error| / sum_j m_j/r_ij^2 p99 {p99(ec):.2e} max {ec.max():.2e}", flush=True)
+        assert p99(ec) <= TOL_P99 and p99(ep) <= TOL_P99
+    else:
+        assert p99(ea) <= TOL_P99 and p99(ep) <= TOL_P99
 
 
 @pytest.mark.parametrize("theta", [0.5, 1.0, 1e-4, 2.0])

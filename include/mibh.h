@@ -60,10 +60,10 @@ typedef struct {
     int32_t precision;  /* MIBH_PLAIN or MIBH_KAHAN per-particle accumulation (default plain) */
     int32_t walk_waves; /* waves of the persistent walk launch; 0 = 4096 (16 per CU of a
                            256-CU MI355X) */
-    int32_t pc_cap;     /* per-wave particle-cell list entries before an evaluation flush
-                           (>= 64; default 8192) */
-    int32_t pp_cap;     /* per-wave particle-particle list entries before a flush
-                           (>= 64; default 4096) */
+    int32_t pc_cap;     /* per-wave particle-cell list entries (in LDS) before an evaluation
+                           flush, 128 <= pc_cap <= 1024 (default 1024) */
+    int32_t pp_cap;     /* per-wave particle-particle list entries (in LDS) before a flush,
+                           128 <= pp_cap <= 512 (default 512) */
 } mibh_params;
 
 /* Fills the defaults listed above. */

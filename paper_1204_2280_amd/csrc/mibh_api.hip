@@ -59,8 +59,8 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 bool params_valid(const mibh_params &p) {
     return p.ncrit >= 1 && p.group_cap >= p.ncrit && p.group_cap <= 64 && p.eps2 >= 0.0f &&
            isfinite(p.eps2) && isfinite(p.G) && (p.precision == MIBH_PLAIN || p.precision == MIBH_KAHAN) &&
-           p.walk_waves >= 0 && p.walk_waves <= (1 << 20) && p.pc_cap >= 64 && p.pp_cap >= 64 &&
-           p.pc_cap <= (1 << 24) && p.pp_cap <= (1 << 24);
+           p.walk_waves >= 0 && p.walk_waves <= (1 << 20) && p.pc_cap >= 128 && p.pp_cap >= 128 &&
+           p.pc_cap <= (int)WALK_PC_LDS && p.pp_cap <= (int)WALK_PP_LDS;
 }
 
 // Assigns every buffer of the layout from `base` (nullptr: sizing only) and
@@ -101,8 +101,6 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.groups = (uint2 *)take(8 * n);
     t.gcounts = (uint2 *)take(8 * n);
     t.wstack = (uint32_t *)take(4 * (size_t)STACK_CAP * waves);
-    t.wpc = (uint32_t *)take(4 * (size_t)p.pc_cap * waves);
-    t.wpp = (uint32_t *)take(4 * (size_t)p.pp_cap * waves);
     t.epart = (double *)take(8 * 2 * ENERGY_BLOCKS + 16);
     t.cap_cells = (unsigned)cap_cells;
     t.n_max = (unsigned)n_max;
@@ -148,8 +146,8 @@ void mibh_default_params(mibh_params *p) {
     p->G = 1.0f;
     p->precision = MIBH_PLAIN;
     p->walk_waves = 0;
-    p->pc_cap = 8192;
-    p->pp_cap = 4096;
+    p->pc_cap = (int32_t)WALK_PC_LDS;
+    p->pp_cap = (int32_t)WALK_PP_LDS;
 }
 
 size_t mibh_workspace_bytes(int64_t n_max, const mibh_params *pp) {

@@ -42,11 +42,16 @@ struct Header {
     unsigned n;
     unsigned ncells;
     unsigned ngroups;
-    unsigned walk_next;     // persistent walk queue head
+    unsigned walk_next[8];  // persistent walk: head of each of the 8 group queues (one per XCD)
     unsigned lvl_begin[24]; // cells of level l are [lvl_begin[l], lvl_begin[l+1]), l = 0..20
     unsigned long long sum_pc, sum_pp;
     unsigned pad[8];
 };
+
+// Walk: LDS capacities per wave (one wave per workgroup).
+constexpr unsigned WALK_LSTACK = 512;   // cell stack in LDS (spills to the global stack)
+constexpr unsigned WALK_PC_LDS = 1024;  // particle-cell list
+constexpr unsigned WALK_PP_LDS = 512;   // particle-particle list
 
 // Device pointers carved from the caller's workspace.
 struct Buffers {
@@ -68,9 +73,7 @@ struct Buffers {
     float4 *ceval;          // cells: [2] (M, Qxx, Qyy, Qzz), (Qxy, Qxz, Qyz, 0)
     uint2 *groups;          // first, level<<8 | count
     uint2 *gcounts;         // n_pc, n_pp
-    uint32_t *wstack;       // per walk wave: STACK_CAP
-    uint32_t *wpc;          // per walk wave: pc_cap
-    uint32_t *wpp;          // per walk wave: pp_cap
+    uint32_t *wstack;       // per walk wave: STACK_CAP (spill of the LDS stack)
     double *epart;          // energy partials [ENERGY_BLOCKS][2]
     unsigned cap_cells, n_max, ntiles_max, nblk_max;
     unsigned walk_waves, pc_cap, pp_cap;

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ pa
         hdr->n = n;
         hdr->ncells = 0;
         hdr->ngroups = 0;
-        hdr->walk_next = 0;
+        for (int q = 0; q < 8; q++) hdr->walk_next[q] = 0;
         hdr->sum_pc = 0;
         hdr->sum_pp = 0;
         for (int l = 0; l < 24; l++) hdr->lvl_begin[l] = 0;
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr,
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
     const int k = hdr->k;
-    if (blockIdx.x == 0 && threadIdx.x == 0) hdr->walk_next = 0;  // the walk that follows starts at group 0
+    if (blockIdx.x == 0 && threadIdx.x < 8) hdr->walk_next[threadIdx.x] = 0;  // queues of the walk that follows
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
         const int lev = (int)(topo[c].w >> 8);
         const double ro = ldexp(inv_theta, k - lev) + delta[c];

@@ -3,16 +3,24 @@
 //
 // One wave64 per group (the vector-machine idea of Barnes 1990: one
 // interaction list shared by a group of nearby particles), persistent waves
-// pulling groups from a device-side queue.
+// pulling groups from eight device-side queues: queue q holds the q-th eighth
+// of the groups in Morton order and is served first by the waves of XCD q
+// (workgroups are dispatched to the 8 XCDs round-robin), so the concurrent
+// groups of one XCD are spatial neighbours sharing most of their cells in that
+// XCD's L2.  A wave whose queue is empty steals from the next one.
 //
-// Traversal: lanes hold up to 64 candidate cells popped from a per-wave stack;
-// each lane applies the opening test of Barnes (1994) for the group's bounding
-// box (float32, fixed operation order); ballots + mbcnt compact accepted cells
-// into the particle-cell list, opened leaves into the particle-particle list
-// (expanded to particle indices) and opened internal cells' children onto the
-// stack.  Lanes pop in stack order and push in lane order, so stack levels
-// never decrease towards the top; then at most one step's pushes (<= 64*8)
-// per level are on the stack at any time, which bounds it by 1 + 20*512.
+// Traversal: lanes hold up to 64 candidate cells popped from a per-wave stack
+// kept in LDS (circular, spilling its bottom to a per-wave global stack when
+// full); each lane applies the opening test of Barnes (1994) for the group's
+// bounding box (float32, fixed operation order); ballots + mbcnt compact
+// accepted cells into the particle-cell list, opened leaves into the
+// particle-particle list (expanded to particle indices) and opened internal
+// cells' children onto the stack.  Lanes pop in stack order and push in lane
+// order, so stack levels never decrease towards the top; then at most one
+// step's pushes (<= 64*8) per level are on the stack at any time, which bounds
+// it by 1 + 20*512 entries.  Both lists live in LDS and are evaluated in whole
+// 64-entry tiles when they fill (the remainder stays), the last partial tile at
+// the end of the group.
 //
 // Evaluation: groups average ~20 particles, so lanes run over the list
 // entries (64 sources per tile) and a wave-uniform loop runs over the group's
@@ -104,7 +112,7 @@ struct WalkArgs {
     const uint32_t *perm;
     const uint2 *groups;
     uint2 *gcounts;
-    uint32_t *wstack, *wpc, *wpp;
+    uint32_t *wstack;
     float *acc, *pot;
     float eps2, G;
     unsigned pc_cap, pp_cap;
@@ -117,9 +125,8 @@ constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
 // `gn` group particles and adds the results into s_res (one value per lane
 // per chunk).
 template <bool KAHAN, bool PC>
-__device__ void flush(const WalkArgs &a, const uint32_t *list, unsigned nlist, unsigned gn, float px, float py,
-                      float pz, float (*s_res)[64], float (*s_cmp)[64]) {
-    __threadfence_block();
+__device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist, unsigned gn, float px, float py,
+                         float pz, float (*s_res)[64], float (*s_cmp)[64]) {
     const unsigned ln = lane64();
     const float eps2 = a.eps2;
     for (unsigned c0 = 0; c0 < gn; c0 += CHUNK) {
@@ -196,29 +203,60 @@ __device__ void flush(const WalkArgs &a, const uint32_t *list, unsigned nlist, u
             for (int j = 0; j < 64; j++) v[j] = v[j] - cv[j];
         }
         const float r = transpose_reduce(v);
-        add<KAHAN>(s_res[c0 / CHUNK][ln], s_cmp[c0 / CHUNK][ln], r);
+        if (KAHAN) add<true>(s_res[c0 / CHUNK][ln], s_cmp[c0 / CHUNK][ln], r);
+        else s_res[c0 / CHUNK][ln] += r;
     }
 }
 
+// Evaluates the list's whole 64-entry tiles (all entries if `all`), moves the
+// remaining entries to the front and returns their number.
+template <bool KAHAN, bool PC>
+__device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bool all, unsigned gn, float px,
+                               float py, float pz, float (*s_res)[64], float (*s_cmp)[64]) {
+    const unsigned ne = all ? n : (n & ~63u);
+    __syncthreads();  // list entries written by other lanes are visible
+    if (ne) evaluate<KAHAN, PC>(a, list, ne, gn, px, py, pz, s_res, s_cmp);
+    const unsigned r = n - ne;
+    if (r) {
+        const unsigned ln = lane64();
+        const unsigned v = ln < r ? list[ne + ln] : 0u;
+        __syncthreads();
+        if (ln < r) list[ln] = v;
+        __syncthreads();
+    }
+    return r;
+}
+
 template <bool KAHAN>
-__global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
+__global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
+    constexpr unsigned MASK = WALK_LSTACK - 1;
+    static_assert((WALK_LSTACK & MASK) == 0 && WALK_LSTACK >= 512, "stack ring must hold one step's pushes");
+    __shared__ uint32_t s_stk[WALK_LSTACK];
+    __shared__ uint32_t s_pc[WALK_PC_LDS];
+    __shared__ uint32_t s_pp[WALK_PP_LDS];
     __shared__ float s_res[4][64];
-    __shared__ float s_cmp[4][64];
+    __shared__ float s_cmp[KAHAN ? 4 : 1][64];
     const unsigned ln = lane64();
-    const unsigned slot = blockIdx.x;
-    uint32_t *stk = a.wstack + (size_t)slot * STACK_CAP;
-    uint32_t *pcl = a.wpc + (size_t)slot * a.pc_cap;
-    uint32_t *ppl = a.wpp + (size_t)slot * a.pp_cap;
+    uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
     if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
     const unsigned ngroups = a.hdr->ngroups;
-    const unsigned rounds_cap = a.pp_cap >> 6;  // particles a lane may add per round
+    // particles a lane may add to the particle-particle list per round, so that
+    // a round (<= 64 * per_round) fits after a flush leaves < 64 entries
+    const unsigned per_round = max(1u, (a.pp_cap - 64u) >> 6);
+    unsigned q = blockIdx.x & 7u, exhausted = 0;
     for (;;) {
+        const unsigned qb = (unsigned)(((unsigned long long)ngroups * q) >> 3);
+        const unsigned qe = (unsigned)(((unsigned long long)ngroups * (q + 1)) >> 3);
         // Every lane executes the queue atomic (only lane 0 adds 1) so that no
         // lane-dependent branch sits inside this loop: the compiler may split a
         // loop on a loop-invariant divergent condition, which would separate
         // lane 0 from the cross-lane operations of the other lanes.
-        const unsigned g = uniform(atomicAdd(&a.hdr->walk_next, ln == 0 ? 1u : 0u));
-        if (g >= ngroups) break;
+        const unsigned g = qb + uniform(atomicAdd(&a.hdr->walk_next[q], ln == 0 ? 1u : 0u));
+        if (g >= qe) {
+            if (++exhausted == 8) break;
+            q = (q + 1) & 7u;
+            continue;
+        }
         const uint2 gr = a.groups[g];
         const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform(gr.y >> 8);
         const float4 p = a.spos[gf + min(ln, gn - 1)];
@@ -233,18 +271,30 @@ __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
             bmax.z = fmaxf(bmax.z, __shfl_xor(bmax.z, o, 64));
         }
 #pragma unroll
-        for (int c = 0; c < 4; c++) { s_res[c][ln] = 0.0f; s_cmp[c][ln] = 0.0f; }
+        for (int c = 0; c < 4; c++) {
+            s_res[c][ln] = 0.0f;
+            if (KAHAN) s_cmp[c][ln] = 0.0f;
+        }
 
-        unsigned top = 1, npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
+        // logical stack = global spill [0, gtop) followed by the LDS ring [sb, st)
+        unsigned sb = 0, st = 1, gtop = 0;
+        unsigned npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
         bool overflow = false;
-        stk[0] = 0u;  // the root (all lanes store the same value)
-        __threadfence_block();
-        while (top > 0) {
-            const unsigned m = min(top, 64u);
-            const unsigned base = top - m;
+        s_stk[0] = 0u;  // the root (every lane stores the same value)
+        __syncthreads();
+        while (st != sb || gtop > 0) {
+            if (st == sb) {  // LDS part empty: refill from the top of the global spill
+                const unsigned k = min(gtop, WALK_LSTACK / 2);
+                __threadfence_block();
+                for (unsigned i = ln; i < k; i += 64) s_stk[(sb - k + i) & MASK] = gstk[gtop - k + i];
+                sb -= k;
+                gtop -= k;
+                __syncthreads();
+            }
+            const unsigned m = min(st - sb, 64u);
             const bool valid = ln < m;
-            const unsigned c = valid ? stk[base + ln] : 0u;
-            top = base;
+            const unsigned c = valid ? s_stk[(st - m + ln) & MASK] : 0u;
+            st -= m;
             const uint4 t = a.topo[c];
             const float4 mc = a.cmac[c];
             const unsigned lvl = t.w >> 8, nch = t.w & 255u;
@@ -257,25 +307,21 @@ __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
             // accepted cells -> particle-cell list
             const unsigned long long am = __ballot(accept);
             const unsigned na = (unsigned)__popcll(am);
-            if (npc + na > a.pc_cap) {
-                flush<KAHAN, true>(a, pcl, npc, gn, p.x, p.y, p.z, s_res, s_cmp);
-                npc = 0;
-            }
-            if (accept) pcl[npc + rank_below(am)] = c;
+            if (npc + na > a.pc_cap)
+                npc = flush_list<KAHAN, true>(a, s_pc, npc, false, gn, p.x, p.y, p.z, s_res, s_cmp);
+            if (accept) s_pc[npc + rank_below(am)] = c;
             npc += na;
             tot_pc += na;
 
-            // opened leaves -> particle-particle list, in rounds bounded by the capacity
+            // opened leaves -> particle-particle list, in rounds that fit the list
             unsigned rem = leaf ? t.y : 0u, src = t.x;
             while (__ballot(rem > 0)) {
-                const unsigned take = min(rem, rounds_cap);
+                const unsigned take = min(rem, per_round);
                 unsigned sum;
                 const unsigned off = wave_excl_scan(take, &sum);
-                if (npp + sum > a.pp_cap) {
-                    flush<KAHAN, false>(a, ppl, npp, gn, p.x, p.y, p.z, s_res, s_cmp);
-                    npp = 0;
-                }
-                for (unsigned j = 0; j < take; j++) ppl[npp + off + j] = src + j;
+                if (npp + sum > a.pp_cap)
+                    npp = flush_list<KAHAN, false>(a, s_pp, npp, false, gn, p.x, p.y, p.z, s_res, s_cmp);
+                for (unsigned j = 0; j < take; j++) s_pp[npp + off + j] = src + j;
                 npp += sum;
                 tot_pp += sum;
                 rem -= take;
@@ -286,20 +332,29 @@ __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
             unsigned nsum;
             const unsigned nc = push ? nch : 0u;
             const unsigned off = wave_excl_scan(nc, &nsum);
-            if (top + nsum > STACK_CAP) {
-                overflow = true;
-                break;
+            const unsigned used = st - sb;
+            if (used + nsum > WALK_LSTACK) {  // spill the bottom of the LDS ring
+                const unsigned need = used + nsum - WALK_LSTACK;
+                const unsigned sp = min(used, max(need, WALK_LSTACK / 2));
+                if (gtop + sp > STACK_CAP) {
+                    overflow = true;
+                    break;
+                }
+                for (unsigned i = ln; i < sp; i += 64) gstk[gtop + i] = s_stk[(sb + i) & MASK];
+                sb += sp;
+                gtop += sp;
+                __syncthreads();
             }
-            for (unsigned j = 0; j < nc; j++) stk[top + off + j] = t.z + j;
-            top += nsum;
-            __threadfence_block();
+            for (unsigned j = 0; j < nc; j++) s_stk[(st + off + j) & MASK] = t.z + j;
+            st += nsum;
+            __syncthreads();
         }
         if (overflow) {
             atomicOr(&a.hdr->flags, FLAG_STACK);
             continue;
         }
-        if (npc) flush<KAHAN, true>(a, pcl, npc, gn, p.x, p.y, p.z, s_res, s_cmp);
-        if (npp) flush<KAHAN, false>(a, ppl, npp, gn, p.x, p.y, p.z, s_res, s_cmp);
+        if (npc) flush_list<KAHAN, true>(a, s_pc, npc, true, gn, p.x, p.y, p.z, s_res, s_cmp);
+        if (npp) flush_list<KAHAN, false>(a, s_pp, npp, true, gn, p.x, p.y, p.z, s_res, s_cmp);
 
         // results back to the caller's order
         const unsigned idx = bitrev6(ln);
@@ -334,8 +389,6 @@ hipError_t launch_walk(const Buffers &b, unsigned n, float eps2, float G, int pr
     a.groups = b.groups;
     a.gcounts = b.gcounts;
     a.wstack = b.wstack;
-    a.wpc = b.wpc;
-    a.wpp = b.wpp;
     a.acc = acc;
     a.pot = pot;
     a.eps2 = eps2;

@@ -45,7 +45,8 @@ def test_host_only_entry_points(lib):
     assert mibh.workspace_bytes(1 << 31, p) == 0
     assert mibh.workspace_bytes(100, mibh.default_params(ncrit=65)) == 0
     assert mibh.workspace_bytes(100, mibh.default_params(group_cap=65)) == 0
-    assert mibh.workspace_bytes(100, mibh.default_params(pc_cap=63)) == 0
+    assert mibh.workspace_bytes(100, mibh.default_params(pc_cap=127)) == 0
+    assert mibh.workspace_bytes(100, mibh.default_params(pc_cap=4096)) == 0
     assert lib.mibh_status_string(-5) == b"MIBH_EOVERFLOW"
     h = C.c_void_p()
     # invalid workspace pointer is rejected before any device call

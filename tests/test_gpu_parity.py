@@ -118,7 +118,7 @@ def test_repeated_walks_and_determinism(ctx, orc):
 def test_small_list_capacities_force_flushes(orc):
     """Tiny per-wave list capacities exercise the mid-traversal evaluation flushes."""
     pos, mass = _case("plummer_5003")
-    c = gpu_context(6000, pc_cap=64, pp_cap=64, walk_waves=37)
+    c = gpu_context(6000, pc_cap=128, pp_cap=128, walk_waves=37)
     g = run_gpu(c, pos, mass, 0.75, exports=("counts",))
     T = orc.Tree(pos, mass)
     T.walk(0.75)

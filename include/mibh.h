@@ -64,6 +64,8 @@ typedef struct {
                            flush, 128 <= pc_cap <= 1024 (default 1024) */
     int32_t pp_cap;     /* per-wave particle-particle list entries (in LDS) before a flush,
                            128 <= pp_cap <= 512 (default 512) */
+    int32_t max_systems; /* most independent systems one batched build may hold,
+                            1 <= max_systems <= 256 (default 1) */
 } mibh_params;
 
 /* Fills the defaults listed above. */
@@ -93,6 +95,19 @@ mibh_status mibh_destroy(mibh_ctx *ctx);
  * flagged on the device (ENONFINITE at the next synchronising call). */
 mibh_status mibh_build_tree(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n);
 
+/* Batched tree construction for nsys independent systems (an ensemble): system
+ * s is particles [h_offsets[s], h_offsets[s+1]) of d_pos/d_mass, gets its own
+ * root cube, octree and groups, and interacts only with itself; one
+ * compute_forces call then walks the groups of all systems in one persistent
+ * launch.  h_offsets is a host array of nsys+1 values, 0 = h_offsets[0] <
+ * h_offsets[1] < ... < h_offsets[nsys] = n <= n_max (no empty system), read
+ * before the call returns.  1 <= nsys <= max_systems.  mibh_build_tree is the
+ * nsys = 1 case.  Cells and groups of all systems share one breadth-first
+ * numbering; the level-0 cells are the systems' roots in system order.
+ * Errors: EINVAL. */
+mibh_status mibh_build_tree_batch(mibh_ctx *ctx, const float *d_pos, const float *d_mass,
+                                  const int64_t *h_offsets, int nsys);
+
 /* Multipole moments of every cell (the "tree-properties"): float64 mass,
  * centre of mass and second moments, reduced bottom-up level by level, then
  * the float32 monopole + traceless quadrupole used by the walk.
@@ -110,6 +125,22 @@ mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float 
 mibh_status mibh_forces(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n,
                         float theta, float *d_acc, float *d_pot);
 
+/* Graph capture of one whole step: build (batched, as mibh_build_tree_batch),
+ * multipoles and forces are captured from the context's stream into a HIP graph
+ * and instantiated; nothing runs during the capture.  mibh_graph_launch replays
+ * it on the context's stream with the captured pointers, offsets and theta
+ * (the inputs may change in place between replays).  The step holds no
+ * allocation, memset or synchronisation, so the whole step is one graph launch.
+ * The context's stream must not be the null stream.
+ * Errors: EINVAL, EHIP; graph_launch: ESTATE if nothing was captured. */
+mibh_status mibh_graph_capture(mibh_ctx *ctx, const float *d_pos, const float *d_mass,
+                               const int64_t *h_offsets, int nsys, float theta, float *d_acc,
+                               float *d_pot);
+mibh_status mibh_graph_launch(mibh_ctx *ctx);
+
+/* Changes the stream later calls enqueue on (hipStream_t; NULL = null stream). */
+mibh_status mibh_set_stream(mibh_ctx *ctx, void *stream);
+
 /* Synchronises: waits for the context's stream and reports device flags
  * (ENONFINITE, EOVERFLOW) raised since the last build_tree. */
 mibh_status mibh_sync(mibh_ctx *ctx);
@@ -118,7 +149,8 @@ mibh_status mibh_sync(mibh_ctx *ctx);
 typedef struct {
     int64_t n, ncells, ngroups, nleaves;
     int32_t depth;         /* deepest cell level */
-    int32_t root_k;        /* root cube side is 2^root_k */
+    int32_t root_k;        /* root cube side of system 0 is 2^root_k */
+    int32_t nsys;          /* systems of the current tree */
     uint64_t sum_pc;       /* sum over particles of their group's particle-cell count */
     uint64_t sum_pp;       /* sum over particles of their group's particle-particle count */
     uint32_t flags;        /* device flags: 1 non-finite, 2 negative mass, 4 stack, 8 cell capacity */
@@ -135,8 +167,8 @@ mibh_status mibh_energy(mibh_ctx *ctx, const float *d_vel, double *T, double *W)
  *   MIBH_EXPORT_KEYS    uint64 [n]        sorted Morton keys
  *   MIBH_EXPORT_PERM    uint32 [n]        sorted position -> input index
  *   MIBH_EXPORT_CELLS   uint32 [ncells][4] first, count, child_first (0 = leaf),
- *                                         level << 8 | nchild
- *   MIBH_EXPORT_GROUPS  uint32 [ngroups][2] first, level << 8 | count
+ *                                         system << 16 | level << 8 | nchild
+ *   MIBH_EXPORT_GROUPS  uint32 [ngroups][2] first, system << 16 | level << 8 | count
  *   MIBH_EXPORT_COUNTS  uint32 [ngroups][2] particle-cell count, particle-particle count
  *   MIBH_EXPORT_MULTIPOLES float64 [ncells][10] M, com x y z, S xx yy zz xy xz yz
  *   MIBH_EXPORT_DELTA   float64 [ncells]  |com - geometric centre|

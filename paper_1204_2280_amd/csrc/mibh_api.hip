@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 using namespace mibh;
@@ -15,6 +16,13 @@ using namespace mibh;
 struct mibh_ctx {
     mibh_params p;
     int64_t n_max;
+    int nsys;                 // systems of the current tree
+    hipGraph_t graph;         // captured step (mibh_graph_capture)
+    hipGraphExec_t graph_exec;
+    int graph_nsys;
+    int64_t graph_n;
+    const float *graph_pos, *graph_mass;
+    float *graph_acc, *graph_pot;
     hipStream_t stream;
     int device;
     Buffers b;
@@ -56,8 +64,20 @@ constexpr int DEFAULT_WALK_WAVES = 4096;  // 16 per compute unit on 256 CUs
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
+// System offsets travel to the device as a kernel argument, so a captured
+// graph holds them by value and no host staging buffer is needed.
+struct SysOffsets {
+    unsigned nsys;
+    unsigned off[MAX_SYSTEMS + 1];
+};
+
+__global__ void k_set_offsets(SysOffsets o, uint32_t *__restrict__ sys_off) {
+    for (unsigned i = threadIdx.x; i <= o.nsys; i += blockDim.x) sys_off[i] = o.off[i];
+}
+
 bool params_valid(const mibh_params &p) {
     return p.ncrit >= 1 && p.group_cap >= p.ncrit && p.group_cap <= 64 && p.eps2 >= 0.0f &&
+           p.max_systems >= 1 && p.max_systems <= MAX_SYSTEMS &&
            isfinite(p.eps2) && isfinite(p.G) && (p.precision == MIBH_PLAIN || p.precision == MIBH_KAHAN) &&
            p.walk_waves >= 0 && p.walk_waves <= (1 << 20) && p.pc_cap >= 128 && p.pp_cap >= 128 &&
            p.pc_cap <= (int)WALK_PC_LDS && p.pp_cap <= (int)WALK_PP_LDS;
@@ -79,9 +99,14 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     // particles each and every particle has at most 20 internal ancestors
     const size_t cap_cells = n + (20 * n) / (size_t)(p.ncrit + 1) + 2;
     const size_t waves = p.walk_waves ? (size_t)p.walk_waves : DEFAULT_WALK_WAVES;
+    const size_t nsys = (size_t)p.max_systems;
+    const size_t bbox_blocks = nsys * (size_t)std::max(BBOX_MIN_BLOCKS, BBOX_BLOCKS / (int)nsys);
     Buffers t;
     t.hdr = (Header *)take(sizeof(Header));
-    t.bbox_part = (float *)take(sizeof(float) * 8 * BBOX_BLOCKS);
+    t.cube = (SysCube *)take(sizeof(SysCube) * nsys);
+    t.sys_off = (uint32_t *)take(4 * (nsys + 1));
+    t.sys8 = (uint8_t *)take(nsys > 1 ? n : 1);
+    t.bbox_part = (float *)take(sizeof(float) * 8 * std::max(bbox_blocks, (size_t)BBOX_BLOCKS));
     t.keys[0] = (uint64_t *)take(8 * n);
     t.keys[1] = (uint64_t *)take(8 * n);
     t.vals[0] = (uint32_t *)take(4 * n);
@@ -109,6 +134,7 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.walk_waves = (unsigned)waves;
     t.pc_cap = (unsigned)p.pc_cap;
     t.pp_cap = (unsigned)p.pp_cap;
+    t.max_systems = (unsigned)p.max_systems;
     if (b) *b = t;
     return off;
 }
@@ -148,6 +174,7 @@ void mibh_default_params(mibh_params *p) {
     p->walk_waves = 0;
     p->pc_cap = (int32_t)WALK_PC_LDS;
     p->pp_cap = (int32_t)WALK_PP_LDS;
+    p->max_systems = 1;
 }
 
 size_t mibh_workspace_bytes(int64_t n_max, const mibh_params *pp) {
@@ -181,6 +208,9 @@ mibh_status mibh_create(const mibh_params *pp, int64_t n_max, void *d_workspace,
     c->acc = c->pot = nullptr;
     c->events = nullptr;
     c->prof_max = c->prof_step = 0;
+    c->nsys = 1;
+    c->graph = nullptr;
+    c->graph_exec = nullptr;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
         delete c;
@@ -218,40 +248,61 @@ mibh_status mibh_destroy(mibh_ctx *ctx) {
     if (!ctx) return MIBH_OK;
     (void)hipSetDevice(ctx->device);
     free_events(ctx);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->h_energy) (void)hipHostFree(ctx->h_energy);
     delete ctx;
     return MIBH_OK;
 }
 
-mibh_status mibh_build_tree(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n) {
+mibh_status mibh_build_tree_batch(mibh_ctx *ctx, const float *d_pos, const float *d_mass,
+                                  const int64_t *h_offsets, int nsys) {
     mibh_status st = check_ctx(ctx);
     if (st) return st;
-    if (!d_pos || !d_mass) return fail(MIBH_EINVAL, "null input pointer");
-    if (n < 1 || n > ctx->n_max) return fail(MIBH_EINVAL, "n = %lld outside [1, %lld]", (long long)n,
-                                             (long long)ctx->n_max);
-    const unsigned un = (unsigned)n;
+    if (!d_pos || !d_mass || !h_offsets) return fail(MIBH_EINVAL, "null input pointer");
+    if (nsys < 1 || nsys > ctx->p.max_systems)
+        return fail(MIBH_EINVAL, "nsys = %d outside [1, max_systems = %d]", nsys, ctx->p.max_systems);
+    if (h_offsets[0] != 0) return fail(MIBH_EINVAL, "offsets[0] must be 0");
+    for (int s = 0; s < nsys; s++)
+        if (h_offsets[s + 1] <= h_offsets[s]) return fail(MIBH_EINVAL, "system %d is empty or offsets decrease", s);
+    const int64_t n = h_offsets[nsys];
+    if (n > ctx->n_max) return fail(MIBH_EINVAL, "n = %lld > n_max = %lld", (long long)n, (long long)ctx->n_max);
+    SysOffsets o;
+    o.nsys = (unsigned)nsys;
+    for (int s = 0; s <= nsys; s++) o.off[s] = (unsigned)h_offsets[s];
+    const unsigned un = (unsigned)n, us = (unsigned)nsys;
     hipStream_t s = ctx->stream;
     if ((st = mark(ctx, -1))) return st;
-    HIP_TRY(launch_bbox(ctx->b, d_pos, d_mass, un, s), "bbox");
-    HIP_TRY(launch_keys(ctx->b, d_pos, un, s), "keys");
-    HIP_TRY(launch_sort(ctx->b, un, s), "sort");
+    hipLaunchKernelGGL(k_set_offsets, dim3(1), dim3(256), 0, s, o, ctx->b.sys_off);
+    HIP_TRY(hipGetLastError(), "set_offsets");
+    HIP_TRY(launch_bbox(ctx->b, d_pos, d_mass, un, us, s), "bbox");
+    HIP_TRY(launch_keys(ctx->b, d_pos, un, us, s), "keys");
+    HIP_TRY(launch_sort(ctx->b, un, us, s), "sort");
     if ((st = mark(ctx, MIBH_STAGE_SORT))) return st;
-    HIP_TRY(launch_reorder(ctx->b, d_pos, d_mass, un, s), "reorder");
+    HIP_TRY(launch_reorder(ctx->b, d_pos, d_mass, un, us, s), "reorder");
     if ((st = mark(ctx, MIBH_STAGE_MOVE))) return st;
-    HIP_TRY(launch_build(ctx->b, un, ctx->p.ncrit, ctx->p.group_cap, s), "build");
+    HIP_TRY(launch_build(ctx->b, un, us, ctx->p.ncrit, ctx->p.group_cap, s), "build");
     if ((st = mark(ctx, MIBH_STAGE_BUILD))) return st;
     ctx->n = n;
+    ctx->nsys = nsys;
     ctx->pos = d_pos;
     ctx->mass = d_mass;
     ctx->state = 1;
     return MIBH_OK;
 }
 
+mibh_status mibh_build_tree(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n) {
+    if (ctx && (n < 1 || n > ctx->n_max))
+        return fail(MIBH_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)ctx->n_max);
+    const int64_t off[2] = {0, n};
+    return mibh_build_tree_batch(ctx, d_pos, d_mass, off, 1);
+}
+
 mibh_status mibh_compute_multipoles(mibh_ctx *ctx) {
     mibh_status st = check_ctx(ctx);
     if (st) return st;
     if (ctx->state < 1) return fail(MIBH_ESTATE, "compute_multipoles before build_tree");
-    HIP_TRY(launch_multipoles(ctx->b, ctx->stream), "multipoles");
+    HIP_TRY(launch_multipoles(ctx->b, (unsigned)ctx->nsys, ctx->stream), "multipoles");
     if ((st = mark(ctx, MIBH_STAGE_MULTIPOLES))) return st;
     ctx->state = 2;
     return MIBH_OK;
@@ -264,10 +315,10 @@ mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float 
     if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
     if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
     const double inv_theta = 1.0 / (double)theta;
-    HIP_TRY(launch_mac_prep(ctx->b, inv_theta, ctx->stream), "mac_prep");
+    HIP_TRY(launch_mac_prep(ctx->b, (unsigned)ctx->nsys, inv_theta, ctx->stream), "mac_prep");
     if ((st = mark(ctx, MIBH_STAGE_MACPREP))) return st;
-    HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, ctx->p.eps2, ctx->p.G, ctx->p.precision, d_acc, d_pot,
-                        ctx->stream),
+    HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, (unsigned)ctx->nsys, ctx->p.eps2, ctx->p.G, ctx->p.precision,
+                        d_acc, d_pot, ctx->stream),
             "walk");
     if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;
     if (ctx->events && ctx->prof_step < ctx->prof_max) ctx->prof_step++;
@@ -310,7 +361,10 @@ mibh_status mibh_stats(mibh_ctx *ctx, mibh_stats_t *out) {
     out->n = ctx->n;
     out->ncells = h.ncells;
     out->ngroups = h.ngroups;
-    out->root_k = h.k;
+    SysCube c0;
+    HIP_TRY(hipMemcpy(&c0, ctx->b.cube, sizeof(SysCube), hipMemcpyDeviceToHost), "hipMemcpy(cube)");
+    out->root_k = c0.k;
+    out->nsys = ctx->nsys;
     out->flags = h.flags;
     int depth = 0;
     for (int l = 0; l <= KEY_LEVELS; l++)
@@ -399,8 +453,8 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
         return fail(MIBH_ESTATE, "export of multipoles before compute_multipoles");
     const void *src = nullptr;
     switch (what) {
-        case MIBH_EXPORT_KEYS: src = ctx->b.keys[0]; break;
-        case MIBH_EXPORT_PERM: src = ctx->b.vals[0]; break;
+        case MIBH_EXPORT_KEYS: src = ctx->b.keys[sorted_buffer((unsigned)ctx->nsys)]; break;
+        case MIBH_EXPORT_PERM: src = ctx->b.vals[sorted_buffer((unsigned)ctx->nsys)]; break;
         case MIBH_EXPORT_CELLS: src = ctx->b.topo; break;
         case MIBH_EXPORT_GROUPS: src = ctx->b.groups; break;
         case MIBH_EXPORT_COUNTS: src = ctx->b.gcounts; break;
@@ -412,6 +466,70 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
     }
     if (need) HIP_TRY(hipMemcpyAsync(d_dst, src, need, hipMemcpyDeviceToDevice, ctx->stream), "hipMemcpyAsync(export)");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return MIBH_OK;
+}
+
+mibh_status mibh_graph_capture(mibh_ctx *ctx, const float *d_pos, const float *d_mass, const int64_t *h_offsets,
+                               int nsys, float theta, float *d_acc, float *d_pot) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!ctx->stream) return fail(MIBH_EINVAL, "graph capture needs a non-null stream");
+    if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
+    if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    hipEvent_t *saved = ctx->events;  // no stage events inside a graph
+    ctx->events = nullptr;
+    HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    st = mibh_build_tree_batch(ctx, d_pos, d_mass, h_offsets, nsys);
+    if (!st) st = mibh_compute_multipoles(ctx);
+    if (!st) st = mibh_compute_forces(ctx, theta, d_acc, d_pot);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    ctx->events = saved;
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        ctx->state = 0;
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        ctx->state = 0;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    ctx->graph = g;
+    ctx->graph_nsys = nsys;
+    ctx->graph_n = h_offsets[nsys];
+    ctx->graph_pos = d_pos;
+    ctx->graph_mass = d_mass;
+    ctx->graph_acc = d_acc;
+    ctx->graph_pot = d_pot;
+    ctx->state = 0;  // capture enqueued no work
+    return MIBH_OK;
+}
+
+mibh_status mibh_graph_launch(mibh_ctx *ctx) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!ctx->graph_exec) return fail(MIBH_ESTATE, "no captured graph");
+    HIP_TRY(hipGraphLaunch(ctx->graph_exec, ctx->stream), "hipGraphLaunch");
+    ctx->nsys = ctx->graph_nsys;
+    ctx->n = ctx->graph_n;
+    ctx->pos = ctx->graph_pos;
+    ctx->mass = ctx->graph_mass;
+    ctx->acc = ctx->graph_acc;
+    ctx->pot = ctx->graph_pot;
+    ctx->state = 3;
+    return MIBH_OK;
+}
+
+mibh_status mibh_set_stream(mibh_ctx *ctx, void *stream) {
+    if (!ctx) return fail(MIBH_EINVAL, "null context");
+    ctx->stream = (hipStream_t)stream;
     return MIBH_OK;
 }
 

@@ -34,10 +34,18 @@ enum : unsigned {
     FLAG_CELLCAP = 8u,
 };
 
+// Per-system root cube: corner lo (x, y, z) and side 2^k.
+struct SysCube {
+    float lo[3];
+    int k;
+};
+
+constexpr int MAX_SYSTEMS = 256;        // systems per batch (one extra 8-bit sort pass)
+constexpr int BBOX_MIN_BLOCKS = 16;     // bounding-box blocks per system at least
+
 // Device-resident per-context state, rewritten by every build.
 struct Header {
-    float lo[4];            // root cube corner (x, y, z)
-    int k;                  // root cube side 2^k
+    unsigned nsys;          // systems in the current batch (1 for a single system)
     unsigned flags;
     unsigned n;
     unsigned ncells;
@@ -56,7 +64,10 @@ constexpr unsigned WALK_PP_LDS = 512;   // particle-particle list
 // Device pointers carved from the caller's workspace.
 struct Buffers {
     Header *hdr;
-    float *bbox_part;       // [BBOX_BLOCKS][8]
+    SysCube *cube;          // [max_systems]
+    uint32_t *sys_off;      // [max_systems + 1] first particle of each system (input = sorted order)
+    uint8_t *sys8;          // [n] system of each input particle (batches only)
+    float *bbox_part;       // [max_systems][bbox blocks per system][8]
     uint64_t *keys[2];
     uint32_t *vals[2];
     uint32_t *hist;         // [RADIX][ntiles]
@@ -66,29 +77,42 @@ struct Buffers {
     uchar4 *lvinfo;         // per particle: first level started, leaf level, group level, group start
     uint32_t *blkcnt;       // [NCOUNTERS][nblk]
     uint32_t *ctot;         // [NCOUNTERS]
-    uint4 *topo;            // cells: first, count, child_first, level<<8 | nchild
+    uint4 *topo;            // cells: first, count, child_first, system<<16 | level<<8 | nchild
     double *mp;             // cells: [10] M, com xyz, S xx yy zz xy xz yz
     double *delta;          // cells: |com - centre|
     float4 *cmac;           // cells: com32 xyz, r_open^2
     float4 *ceval;          // cells: [2] (M, Qxx, Qyy, Qzz), (Qxy, Qxz, Qyz, 0)
-    uint2 *groups;          // first, level<<8 | count
+    uint2 *groups;          // first, system<<16 | level<<8 | count
     uint2 *gcounts;         // n_pc, n_pp
     uint32_t *wstack;       // per walk wave: STACK_CAP (spill of the LDS stack)
     double *epart;          // energy partials [ENERGY_BLOCKS][2]
     unsigned cap_cells, n_max, ntiles_max, nblk_max;
-    unsigned walk_waves, pc_cap, pp_cap;
+    unsigned walk_waves, pc_cap, pp_cap, max_systems;
 };
 
+// System of sorted or input position i: the s with sys_off[s] <= i < sys_off[s+1].
+__device__ __forceinline__ unsigned system_of(const uint32_t *__restrict__ sys_off, unsigned nsys, unsigned i) {
+    unsigned lo = 0, hi = nsys;  // sys_off[lo] <= i < sys_off[hi]
+    while (hi - lo > 1) {
+        const unsigned mid = (lo + hi) >> 1;
+        if (sys_off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // Host launchers (kernels live in the .hip files).
-hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, hipStream_t s);
-hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, hipStream_t s);
-hipError_t launch_sort(const Buffers &b, unsigned n, hipStream_t s);
-hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n,
+hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
+                       hipStream_t s);
+hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, unsigned nsys, hipStream_t s);
+hipError_t launch_sort(const Buffers &b, unsigned n, unsigned nsys, hipStream_t s);
+// buffer (0 or 1) that holds the sorted keys and permutation after launch_sort
+inline int sorted_buffer(unsigned nsys) { return nsys > 1 ? (SORT_PASSES + 1) & 1 : SORT_PASSES & 1; }
+hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
                           hipStream_t s);
-hipError_t launch_build(const Buffers &b, unsigned n, int ncrit, int gcap, hipStream_t s);
-hipError_t launch_multipoles(const Buffers &b, hipStream_t s);
-hipError_t launch_mac_prep(const Buffers &b, double inv_theta, hipStream_t s);
-hipError_t launch_walk(const Buffers &b, unsigned n, float eps2, float G, int precision,
+hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, int gcap, hipStream_t s);
+hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s);
+hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double inv_theta, hipStream_t s);
+hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
                        float *acc, float *pot, hipStream_t s);
 hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
                          unsigned n, double *d_out2, hipStream_t s);

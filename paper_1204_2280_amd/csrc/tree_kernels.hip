@@ -100,6 +100,7 @@ __device__ __forceinline__ int shared_digits(uint64_t a, uint64_t b) {
 // digits (n if none): galloping search over the sorted keys.
 __device__ __forceinline__ unsigned run_end(const uint64_t *__restrict__ keys, unsigned n, unsigned i,
                                             int lev) {
+    // n is the end of i's system: keys of different systems are never compared
     if (lev == 0) return n;
     const int sh = 3 * (KEY_LEVELS - lev);
     const uint64_t p = keys[i] >> sh;
@@ -118,15 +119,18 @@ __device__ __forceinline__ unsigned run_end(const uint64_t *__restrict__ keys, u
 }
 
 // --------------------------------------------------------------------------
-// Bounding cube
+// Bounding cube, one per system (grid row y = system)
 // --------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ pos,
-                                                      const float *__restrict__ mass, unsigned n,
+                                                      const float *__restrict__ mass,
+                                                      const uint32_t *__restrict__ sys_off,
                                                       float *__restrict__ part) {
+    const unsigned sys = blockIdx.y;
+    const unsigned b0 = sys_off[sys], b1 = sys_off[sys + 1];
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     unsigned flags = 0;
-    for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    for (unsigned i = b0 + blockIdx.x * 256u + threadIdx.x; i < b1; i += gridDim.x * 256u) {
         const size_t b = (size_t)i * 3;
         const float x[3] = {pos[b], pos[b + 1], pos[b + 2]};
         const float m = mass[i];
@@ -162,22 +166,27 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ 
             }
             s[0][6] = __uint_as_float(__float_as_uint(s[0][6]) | __float_as_uint(s[v][6]));
         }
-        for (int a = 0; a < 7; a++) part[blockIdx.x * 8 + a] = s[0][a];
+        float *o = part + ((size_t)sys * gridDim.x + blockIdx.x) * 8;
+        for (int a = 0; a < 7; a++) o[a] = s[0][a];
     }
 }
 
-// Root cube: corner = per-axis minimum; side 2^k with 2^k > largest extent
-// (frexp of the float64 extent), k = 0 for a zero extent.  Resets the header.
-__global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ part, unsigned n,
-                                                    Header *__restrict__ hdr) {
+// Root cube of each system (one block per system): corner = per-axis minimum,
+// side 2^k with 2^k > largest extent (frexp of the float64 extent), k = 0 for a
+// zero extent.  Block 0 also resets the header.
+__global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ part, unsigned nblocks,
+                                                    unsigned n, unsigned nsys, Header *__restrict__ hdr,
+                                                    SysCube *__restrict__ cube) {
+    const unsigned sys = blockIdx.x;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     unsigned flags = 0;
-    for (unsigned b = threadIdx.x; b < BBOX_BLOCKS; b += 256) {
+    for (unsigned b = threadIdx.x; b < nblocks; b += 256) {
+        const float *p = part + ((size_t)sys * nblocks + b) * 8;
         for (int a = 0; a < 3; a++) {
-            mn[a] = fminf(mn[a], part[b * 8 + a]);
-            mx[a] = fmaxf(mx[a], part[b * 8 + 3 + a]);
+            mn[a] = fminf(mn[a], p[a]);
+            mx[a] = fmaxf(mx[a], p[3 + a]);
         }
-        flags |= __float_as_uint(part[b * 8 + 6]);
+        flags |= __float_as_uint(p[6]);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -214,10 +223,17 @@ __global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ pa
             k = 0;
             for (int a = 0; a < 3; a++) s[0][a] = 0.0f;
         }
-        for (int a = 0; a < 3; a++) hdr->lo[a] = s[0][a];
-        hdr->lo[3] = 0.0f;
-        hdr->k = k;
-        hdr->flags = flags;
+        for (int a = 0; a < 3; a++) cube[sys].lo[a] = s[0][a];
+        cube[sys].k = k;
+        if (flags) atomicOr(&hdr->flags, flags);
+    }
+}
+
+// Header reset, before the per-system reductions of one build.
+__global__ void k_header_reset(unsigned n, unsigned nsys, Header *__restrict__ hdr) {
+    if (threadIdx.x == 0) {
+        hdr->nsys = nsys;
+        hdr->flags = 0;
         hdr->n = n;
         hdr->ncells = 0;
         hdr->ngroups = 0;
@@ -228,9 +244,12 @@ __global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ pa
     }
 }
 
-hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, hipStream_t s) {
-    hipLaunchKernelGGL(k_bbox_partial, dim3(BBOX_BLOCKS), dim3(256), 0, s, pos, mass, n, b.bbox_part);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, b.bbox_part, n, b.hdr);
+hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
+                       hipStream_t s) {
+    const unsigned per = max((unsigned)BBOX_MIN_BLOCKS, (unsigned)BBOX_BLOCKS / nsys);
+    hipLaunchKernelGGL(k_header_reset, dim3(1), dim3(64), 0, s, n, nsys, b.hdr);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(per, nsys), dim3(256), 0, s, pos, mass, b.sys_off, b.bbox_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(nsys), dim3(256), 0, s, b.bbox_part, per, n, nsys, b.hdr, b.cube);
     return hipGetLastError();
 }
 
@@ -239,25 +258,30 @@ hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, un
 // q_x, q_y, q_z at 3b+2, 3b+1, 3b.
 // --------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ pos, unsigned n,
-                                              const Header *__restrict__ hdr,
-                                              uint64_t *__restrict__ keys) {
+__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ pos, unsigned n, unsigned nsys,
+                                              const uint32_t *__restrict__ sys_off,
+                                              const SysCube *__restrict__ cube, uint64_t *__restrict__ keys,
+                                              uint8_t *__restrict__ sys8) {
     const unsigned i = blockIdx.x * 256u + threadIdx.x;
     if (i >= n) return;
-    const double s = ldexp(1.0, KEY_LEVELS - hdr->k);
+    const unsigned sys = nsys > 1 ? system_of(sys_off, nsys, i) : 0u;
+    const SysCube c = cube[sys];
+    const double s = ldexp(1.0, KEY_LEVELS - c.k);
     uint64_t q[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        double f = floor(((double)pos[(size_t)i * 3 + a] - (double)hdr->lo[a]) * s);
+        double f = floor(((double)pos[(size_t)i * 3 + a] - (double)c.lo[a]) * s);
         if (!(f >= 0.0)) f = 0.0;
         if (f > 1048575.0) f = 1048575.0;
         q[a] = (uint64_t)f;
     }
     keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    if (nsys > 1) sys8[i] = (uint8_t)sys;
 }
 
-hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, hipStream_t s) {
-    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, s, pos, n, b.hdr, b.keys[0]);
+hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, unsigned nsys, hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, s, pos, n, nsys, b.sys_off, b.cube,
+                       b.keys[0], b.sys8);
     return hipGetLastError();
 }
 
@@ -268,7 +292,16 @@ hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, hipStream
 // in key order, so equal digits keep their input order.
 // --------------------------------------------------------------------------
 
+// Digit of an element: 8 key bits at `shift`, or (shift < 0) the element's
+// system, looked up by its original index (the last pass of a batch).
+__device__ __forceinline__ unsigned radix_digit(uint64_t key, uint32_t val, int shift,
+                                                const uint8_t *__restrict__ sys8) {
+    return shift >= 0 ? (unsigned)(key >> shift) & (RADIX - 1) : (unsigned)sys8[val];
+}
+
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__restrict__ keys,
+                                                             const uint32_t *__restrict__ vals,
+                                                             const uint8_t *__restrict__ sys8,
                                                              unsigned n, int shift,
                                                              uint32_t *__restrict__ hist,
                                                              unsigned ntiles) {
@@ -281,7 +314,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__r
     for (int t = 0; t < SORT_ITEMS; t++) {
         const unsigned idx = base + t * 64 + ln;
         const bool valid = idx < n;
-        const unsigned d = valid ? (unsigned)(keys[idx] >> shift) & (RADIX - 1) : 0u;
+        const unsigned d = valid ? radix_digit(shift >= 0 ? keys[idx] : 0ull, shift >= 0 ? 0u : vals[idx], shift,
+                                               sys8)
+                                 : 0u;
         const unsigned long long peers = match_digit(d, __ballot(valid));
         if (valid && ln == (unsigned)(__ffsll((long long)peers) - 1)) h[w][d] += __popcll(peers);
     }
@@ -314,8 +349,8 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist,
 
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, unsigned n, int shift, const uint32_t *__restrict__ hist,
-    const uint32_t *__restrict__ btot, unsigned ntiles) {
+    uint32_t *__restrict__ vout, const uint8_t *__restrict__ sys8, unsigned n, int shift,
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ btot, unsigned ntiles) {
     constexpr int NW = SORT_THREADS / 64;
     __shared__ uint32_t wcnt[NW][RADIX];
     __shared__ uint32_t gbase[RADIX];
@@ -339,7 +374,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         const bool valid = idx < n;
         key[t] = valid ? kin[idx] : 0ull;
         val[t] = valid ? (vin ? vin[idx] : idx) : 0u;
-        const unsigned d = (unsigned)(key[t] >> shift) & (RADIX - 1);
+        const unsigned d = valid ? radix_digit(key[t], val[t], shift, sys8) : 0u;
         const unsigned long long peers = match_digit(d, __ballot(valid));
         const unsigned before = wcnt[w][d];
         rank[t] = before + rank_below(peers);
@@ -360,7 +395,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int t = 0; t < SORT_ITEMS; t++) {
         const unsigned idx = base + t * 64 + ln;
         if (idx < n) {
-            const unsigned d = (unsigned)(key[t] >> shift) & (RADIX - 1);
+            const unsigned d = radix_digit(key[t], val[t], shift, sys8);
             const unsigned p = gbase[d] + wcnt[w][d] + rank[t];
             kout[p] = key[t];
             vout[p] = val[t];
@@ -368,17 +403,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
 }
 
-hipError_t launch_sort(const Buffers &b, unsigned n, hipStream_t s) {
+// 8 passes over the 60-bit keys; a batch adds a last pass by system, which
+// gathers each system's particles (in key order) into its input range.
+hipError_t launch_sort(const Buffers &b, unsigned n, unsigned nsys, hipStream_t s) {
     const unsigned ntiles = (n + SORT_TILE - 1) / SORT_TILE;
-    for (int pass = 0; pass < SORT_PASSES; pass++) {
+    const int passes = SORT_PASSES + (nsys > 1 ? 1 : 0);
+    for (int pass = 0; pass < passes; pass++) {
         const int src = pass & 1, dst = src ^ 1;
-        const int shift = pass * RADIX_BITS;
-        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src], n, shift,
-                           b.hist, ntiles);
+        const int shift = pass < SORT_PASSES ? pass * RADIX_BITS : -1;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src], b.vals[src],
+                           b.sys8, n, shift, b.hist, ntiles);
         hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(256), 0, s, b.hist, ntiles, b.btot);
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src],
                            pass == 0 ? (const uint32_t *)nullptr : b.vals[src], b.keys[dst], b.vals[dst],
-                           n, shift, b.hist, b.btot, ntiles);
+                           b.sys8, n, shift, b.hist, b.btot, ntiles);
     }
     return hipGetLastError();
 }
@@ -390,20 +428,23 @@ hipError_t launch_sort(const Buffers &b, unsigned n, hipStream_t s) {
 __global__ __launch_bounds__(256) void k_reorder(const float *__restrict__ pos,
                                                  const float *__restrict__ mass,
                                                  const uint64_t *__restrict__ keys,
-                                                 const uint32_t *__restrict__ perm, unsigned n,
+                                                 const uint32_t *__restrict__ perm, unsigned n, unsigned nsys,
+                                                 const uint32_t *__restrict__ sys_off,
                                                  float4 *__restrict__ spos, int8_t *__restrict__ cl) {
     const unsigned k = blockIdx.x * 256u + threadIdx.x;
     if (k >= n) return;
     const size_t j = perm[k];
     spos[k] = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], mass[j]);
-    cl[k] = k == 0 ? (int8_t)-1 : (int8_t)shared_digits(keys[k - 1], keys[k]);
+    // a system's first particle opens cells at every level, like particle 0
+    const bool start = k == 0 || (nsys > 1 && sys_off[system_of(sys_off, nsys, k)] == k);
+    cl[k] = start ? (int8_t)-1 : (int8_t)shared_digits(keys[k - 1], keys[k]);
 }
 
-hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n,
+hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
                           hipStream_t s) {
-    // after an even number of passes the sorted keys and indices are in buffer 0
-    hipLaunchKernelGGL(k_reorder, dim3((n + 255) / 256), dim3(256), 0, s, pos, mass, b.keys[0], b.vals[0],
-                       n, b.spos, b.cl);
+    const int sb = sorted_buffer(nsys);
+    hipLaunchKernelGGL(k_reorder, dim3((n + 255) / 256), dim3(256), 0, s, pos, mass, b.keys[sb], b.vals[sb],
+                       n, nsys, b.sys_off, b.spos, b.cl);
     return hipGetLastError();
 }
 
@@ -423,8 +464,9 @@ hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass,
 // --------------------------------------------------------------------------
 
 __global__ __launch_bounds__(BUILD_THREADS) void k_build_count(
-    const int8_t *__restrict__ cl, const uint64_t *__restrict__ keys, unsigned n, int ncrit, int gcap,
-    uchar4 *__restrict__ lvinfo, uint32_t *__restrict__ blkcnt, unsigned nblk) {
+    const int8_t *__restrict__ cl, const uint64_t *__restrict__ keys, unsigned n, unsigned nsys,
+    const uint32_t *__restrict__ sys_off, int ncrit, int gcap, uchar4 *__restrict__ lvinfo,
+    uint32_t *__restrict__ blkcnt, unsigned nblk) {
     constexpr int H = MAX_WINDOW;
     constexpr int NW = BUILD_THREADS / 64;
     __shared__ int8_t s_cl[BUILD_THREADS + 2 * H + 2];
@@ -470,7 +512,8 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_count(
         unsigned start = i;
         if (ci >= KEY_LEVELS) {
             const uint64_t key = keys[i];
-            unsigned lo = 0, hi = i;  // first index with keys[index] == key lies in [lo, hi]
+            // first index of the run lies in [start of i's system, i]
+            unsigned lo = nsys > 1 ? sys_off[system_of(sys_off, nsys, i)] : 0u, hi = i;
             while (lo < hi) {
                 const unsigned mid = lo + (hi - lo) / 2;
                 if (keys[mid] < key) lo = mid + 1; else hi = mid;
@@ -525,10 +568,10 @@ __global__ __launch_bounds__(1024) void k_build_scan(uint32_t *__restrict__ blkc
 }
 
 __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
-    const uchar4 *__restrict__ lvinfo, const uint64_t *__restrict__ keys, unsigned n, int gcap,
-    const uint32_t *__restrict__ blkcnt, const uint32_t *__restrict__ ctot, unsigned nblk,
-    Header *__restrict__ hdr, uint4 *__restrict__ topo, uint2 *__restrict__ groups,
-    unsigned cap_cells) {
+    const uchar4 *__restrict__ lvinfo, const uint64_t *__restrict__ keys, unsigned n, unsigned nsys,
+    const uint32_t *__restrict__ sys_off, int gcap, const uint32_t *__restrict__ blkcnt,
+    const uint32_t *__restrict__ ctot, unsigned nblk, Header *__restrict__ hdr, uint4 *__restrict__ topo,
+    uint2 *__restrict__ groups, unsigned cap_cells) {
     constexpr int NW = BUILD_THREADS / 64;
     __shared__ uint32_t s_base[NCOUNTERS];   // first cell number of each level; 0 for groups
     __shared__ uint32_t s_blk[NCOUNTERS];    // this block's offset within each level
@@ -571,6 +614,9 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
         }
     }
     __syncthreads();
+    // the system of this particle and its end: runs never cross systems
+    const unsigned sys = (nsys > 1 && valid) ? system_of(sys_off, nsys, i) : 0u;
+    const unsigned send = nsys > 1 ? (valid ? sys_off[sys + 1] : n) : n;
     // cells, deepest level first so that each cell knows its first child's number
     unsigned next = 0;
     for (int l = KEY_LEVELS; l >= 0; l--) {
@@ -578,9 +624,9 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
         const unsigned long long b = __ballot(pred);
         if (pred) {
             const unsigned idx = s_base[l] + s_blk[l] + s_wpre[w][l] + rank_below(b);
-            const unsigned cnt = run_end(keys, n, i, l) - i;
+            const unsigned cnt = run_end(keys, send, i, l) - i;
             const unsigned cf = l < leaf ? next : 0u;
-            if (idx < cap_cells) topo[idx] = make_uint4(i, cnt, cf, ((unsigned)l << 8));
+            if (idx < cap_cells) topo[idx] = make_uint4(i, cnt, cf, (sys << 16) | ((unsigned)l << 8));
             next = idx;
         }
     }
@@ -589,9 +635,9 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
         if (gstart) {
             const unsigned g = s_blk[NCOUNTERS - 1] + s_wpre[w][NCOUNTERS - 1] + rank_below(b);
             unsigned cnt;
-            if (info.w & 2) cnt = min((unsigned)gcap, run_end(keys, n, i, KEY_LEVELS) - i);
-            else cnt = run_end(keys, n, i, glev) - i;
-            groups[g] = make_uint2(i, ((unsigned)glev << 8) | cnt);
+            if (info.w & 2) cnt = min((unsigned)gcap, run_end(keys, send, i, KEY_LEVELS) - i);
+            else cnt = run_end(keys, send, i, glev) - i;
+            groups[g] = make_uint2(i, (sys << 16) | ((unsigned)glev << 8) | cnt);
         }
     }
 }
@@ -604,7 +650,7 @@ __global__ __launch_bounds__(256) void k_build_nchild(const Header *__restrict__
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
         const uint4 t = topo[c];
         if (t.z == 0) continue;
-        const unsigned l = t.w >> 8;
+        const unsigned l = (t.w >> 8) & 255u;
         const unsigned lend = min(hdr->lvl_begin[l + 2], nc);
         const unsigned end = t.x + t.y;
         unsigned nch = 0;
@@ -612,17 +658,18 @@ __global__ __launch_bounds__(256) void k_build_nchild(const Header *__restrict__
             if (topo[k].x < end) nch++;
             else break;
         }
-        reinterpret_cast<unsigned *>(topo)[4 * (size_t)c + 3] = (l << 8) | nch;
+        reinterpret_cast<unsigned *>(topo)[4 * (size_t)c + 3] = (t.w & 0xffff0000u) | (l << 8) | nch;
     }
 }
 
-hipError_t launch_build(const Buffers &b, unsigned n, int ncrit, int gcap, hipStream_t s) {
+hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, int gcap, hipStream_t s) {
     const unsigned nblk = (n + BUILD_THREADS - 1) / BUILD_THREADS;
-    hipLaunchKernelGGL(k_build_count, dim3(nblk), dim3(BUILD_THREADS), 0, s, b.cl, b.keys[0], n, ncrit,
-                       gcap, b.lvinfo, b.blkcnt, nblk);
+    const uint64_t *keys = b.keys[sorted_buffer(nsys)];
+    hipLaunchKernelGGL(k_build_count, dim3(nblk), dim3(BUILD_THREADS), 0, s, b.cl, keys, n, nsys, b.sys_off,
+                       ncrit, gcap, b.lvinfo, b.blkcnt, nblk);
     hipLaunchKernelGGL(k_build_scan, dim3(NCOUNTERS), dim3(1024), 0, s, b.blkcnt, nblk, b.ctot);
-    hipLaunchKernelGGL(k_build_write, dim3(nblk), dim3(BUILD_THREADS), 0, s, b.lvinfo, b.keys[0], n, gcap,
-                       b.blkcnt, b.ctot, nblk, b.hdr, b.topo, b.groups, b.cap_cells);
+    hipLaunchKernelGGL(k_build_write, dim3(nblk), dim3(BUILD_THREADS), 0, s, b.lvinfo, keys, n, nsys, b.sys_off,
+                       gcap, b.blkcnt, b.ctot, nblk, b.hdr, b.topo, b.groups, b.cap_cells);
     const unsigned grid = min((b.cap_cells + 255u) / 256u, 4096u);
     hipLaunchKernelGGL(k_build_nchild, dim3(grid), dim3(256), 0, s, b.hdr, b.topo, b.cap_cells);
     return hipGetLastError();
@@ -639,7 +686,7 @@ hipError_t launch_build(const Buffers &b, unsigned n, int ncrit, int gcap, hipSt
 // --------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_multipole_level(
-    int lev, const Header *__restrict__ hdr, const uint4 *__restrict__ topo,
+    int lev, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
     const float4 *__restrict__ spos, const uint64_t *__restrict__ keys, double *__restrict__ mp,
     double *__restrict__ delta, float4 *__restrict__ cmac, float4 *__restrict__ ceval,
     unsigned cap_cells) {
@@ -647,12 +694,12 @@ __global__ __launch_bounds__(256) void k_multipole_level(
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
     const unsigned cb = min(hdr->lvl_begin[lev], nc), ce = min(hdr->lvl_begin[lev + 1], nc);
-    const int k = hdr->k;
-    const double lo[3] = {(double)hdr->lo[0], (double)hdr->lo[1], (double)hdr->lo[2]};
-    const double l = ldexp(1.0, k - lev);
     for (unsigned c = cb + blockIdx.x * 256u + threadIdx.x; c < ce; c += gridDim.x * 256u) {
         const uint4 t = topo[c];
         const unsigned nch = t.w & 255u;
+        const SysCube cb3 = cube[t.w >> 16];
+        const double lo[3] = {(double)cb3.lo[0], (double)cb3.lo[1], (double)cb3.lo[2]};
+        const double l = ldexp(1.0, cb3.k - lev);
         const uint64_t pre = keys[t.x] >> (3 * (KEY_LEVELS - lev));
         const double q[3] = {(double)compact3(pre >> 2), (double)compact3(pre >> 1), (double)compact3(pre)};
         double centre[3];
@@ -721,35 +768,37 @@ __global__ __launch_bounds__(256) void k_multipole_level(
     }
 }
 
-hipError_t launch_multipoles(const Buffers &b, hipStream_t s) {
+hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s) {
     const unsigned grid = min((b.cap_cells + 255u) / 256u, 2048u);
     for (int lev = KEY_LEVELS; lev >= 0; lev--)
-        hipLaunchKernelGGL(k_multipole_level, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.topo, b.spos,
-                           b.keys[0], b.mp, b.delta, b.cmac, b.ceval, b.cap_cells);
+        hipLaunchKernelGGL(k_multipole_level, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.cube, b.topo, b.spos,
+                           b.keys[sorted_buffer(nsys)], b.mp, b.delta, b.cmac, b.ceval, b.cap_cells);
     return hipGetLastError();
 }
 
 // r_open = l/theta + delta with l/theta = 2^(k - level) * (1/theta) (exact
 // scaling of the host-rounded reciprocal), squared in float64, rounded once.
-__global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr,
+__global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr, const SysCube *__restrict__ cube,
                                                   const uint4 *__restrict__ topo,
                                                   const double *__restrict__ delta, double inv_theta,
                                                   float4 *__restrict__ cmac, unsigned cap_cells) {
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
-    const int k = hdr->k;
     if (blockIdx.x == 0 && threadIdx.x < 8) hdr->walk_next[threadIdx.x] = 0;  // queues of the walk that follows
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
-        const int lev = (int)(topo[c].w >> 8);
+        const unsigned w = topo[c].w;
+        const int lev = (int)((w >> 8) & 255u);
+        const int k = cube[w >> 16].k;
         const double ro = ldexp(inv_theta, k - lev) + delta[c];
         cmac[c].w = (float)(ro * ro);
     }
 }
 
-hipError_t launch_mac_prep(const Buffers &b, double inv_theta, hipStream_t s) {
+hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double inv_theta, hipStream_t s) {
+    (void)nsys;
     const unsigned grid = min((b.cap_cells + 255u) / 256u, 4096u);
-    hipLaunchKernelGGL(k_mac_prep, dim3(grid), dim3(256), 0, s, b.hdr, b.topo, b.delta, inv_theta, b.cmac,
+    hipLaunchKernelGGL(k_mac_prep, dim3(grid), dim3(256), 0, s, b.hdr, b.cube, b.topo, b.delta, inv_theta, b.cmac,
                        b.cap_cells);
     return hipGetLastError();
 }

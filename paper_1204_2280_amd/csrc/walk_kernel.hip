@@ -258,7 +258,8 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             continue;
         }
         const uint2 gr = a.groups[g];
-        const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform(gr.y >> 8);
+        const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform((gr.y >> 8) & 255u);
+        const unsigned root = uniform(gr.y >> 16);  // level-0 cells are the systems' roots, in system order
         const float4 p = a.spos[gf + min(ln, gn - 1)];
         float3 bmin = make_float3(p.x, p.y, p.z), bmax = bmin;
 #pragma unroll
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
         unsigned sb = 0, st = 1, gtop = 0;
         unsigned npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
         bool overflow = false;
-        s_stk[0] = 0u;  // the root (every lane stores the same value)
+        s_stk[0] = root;  // every lane stores the same value
         __syncthreads();
         while (st != sb || gtop > 0) {
             if (st == sb) {  // LDS part empty: refill from the top of the global spill
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             st -= m;
             const uint4 t = a.topo[c];
             const float4 mc = a.cmac[c];
-            const unsigned lvl = t.w >> 8, nch = t.w & 255u;
+            const unsigned lvl = (t.w >> 8) & 255u, nch = t.w & 255u;
             const bool anc = t.x <= gf && gf < t.x + t.y && lvl <= glev;
             const bool accept = valid && !anc && mac_accept(bmin, bmax, mc);
             const bool opened = valid && !accept;
@@ -376,8 +377,8 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
 
 }  // namespace
 
-hipError_t launch_walk(const Buffers &b, unsigned n, float eps2, float G, int precision, float *acc,
-                       float *pot, hipStream_t s) {
+hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
+                       float *acc, float *pot, hipStream_t s) {
     (void)n;
     WalkArgs a;
     a.hdr = b.hdr;
@@ -385,7 +386,7 @@ hipError_t launch_walk(const Buffers &b, unsigned n, float eps2, float G, int pr
     a.cmac = b.cmac;
     a.ceval = b.ceval;
     a.spos = b.spos;
-    a.perm = b.vals[0];
+    a.perm = b.vals[sorted_buffer(nsys)];
     a.groups = b.groups;
     a.gcounts = b.gcounts;
     a.wstack = b.wstack;

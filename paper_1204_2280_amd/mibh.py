@@ -37,12 +37,12 @@ class MibhError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("ncrit", C.c_int32), ("group_cap", C.c_int32), ("eps2", C.c_float), ("G", C.c_float),
                 ("precision", C.c_int32), ("walk_waves", C.c_int32), ("pc_cap", C.c_int32),
-                ("pp_cap", C.c_int32)]
+                ("pp_cap", C.c_int32), ("max_systems", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("ncells", C.c_int64), ("ngroups", C.c_int64), ("nleaves", C.c_int64),
-                ("depth", C.c_int32), ("root_k", C.c_int32), ("sum_pc", C.c_uint64),
+                ("depth", C.c_int32), ("root_k", C.c_int32), ("nsys", C.c_int32), ("sum_pc", C.c_uint64),
                 ("sum_pp", C.c_uint64), ("flags", C.c_uint32)]
 
 
@@ -64,6 +64,10 @@ def lib():
         L.mibh_create.argtypes = [C.POINTER(Params), i64, P, C.c_size_t, P, C.POINTER(P)]
         L.mibh_destroy.argtypes = [P]
         L.mibh_build_tree.argtypes = [P, P, P, i64]
+        L.mibh_build_tree_batch.argtypes = [P, P, P, P, C.c_int]
+        L.mibh_graph_capture.argtypes = [P, P, P, P, C.c_int, C.c_float, P, P]
+        L.mibh_graph_launch.argtypes = [P]
+        L.mibh_set_stream.argtypes = [P, P]
         L.mibh_compute_multipoles.argtypes = [P]
         L.mibh_compute_forces.argtypes = [P, C.c_float, P, P]
         L.mibh_forces.argtypes = [P, P, P, i64, C.c_float, P, P]
@@ -72,7 +76,8 @@ def lib():
         L.mibh_energy.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.mibh_export_bytes.argtypes = [P, C.c_int, C.POINTER(C.c_size_t)]
         L.mibh_export.argtypes = [P, C.c_int, P, C.c_size_t]
-        for f in ("mibh_create", "mibh_destroy", "mibh_build_tree", "mibh_compute_multipoles",
+        for f in ("mibh_create", "mibh_destroy", "mibh_build_tree", "mibh_build_tree_batch",
+                  "mibh_graph_capture", "mibh_graph_launch", "mibh_set_stream", "mibh_compute_multipoles",
                   "mibh_compute_forces", "mibh_forces", "mibh_sync", "mibh_stats", "mibh_energy",
                   "mibh_export_bytes", "mibh_export"):
             getattr(L, f).restype = st
@@ -170,6 +175,49 @@ class Context:
         self.n = n
         self._keep = (pos, mass)
 
+    def build_tree_batch(self, pos, mass, offsets):
+        """Independent systems: system s = rows offsets[s]:offsets[s+1] (host ints)."""
+        import numpy as np
+        import torch
+        _require(pos, torch.float32, (3,), self.device, "pos")
+        _require(mass, torch.float32, (), self.device, "mass")
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        nsys = len(off) - 1
+        if nsys < 1 or off[-1] != pos.shape[0] or mass.shape[0] != pos.shape[0]:
+            raise ValueError("offsets must run from 0 to the number of particles")
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_build_tree_batch(self.handle, pos.data_ptr(), mass.data_ptr(), off.ctypes.data, nsys))
+        self.n = int(off[-1])
+        self._keep = (pos, mass)
+
+    def forces_batch(self, pos, mass, offsets, theta: float, acc=None, pot=None):
+        self.build_tree_batch(pos, mass, offsets)
+        self.compute_multipoles()
+        return self.compute_forces(theta, acc, pot)
+
+    def set_stream(self, stream):
+        _check(lib().mibh_set_stream(self.handle, stream.cuda_stream))
+        self.stream = stream
+
+    def graph_capture(self, pos, mass, offsets, theta: float, acc, pot):
+        """Captures one whole step into a HIP graph (see mibh_graph_capture)."""
+        import numpy as np
+        import torch
+        for t, name, tail in ((pos, "pos", (3,)), (acc, "acc", (3,))):
+            _require(t, torch.float32, tail, self.device, name)
+        for t, name in ((mass, "mass"), (pot, "pot")):
+            _require(t, torch.float32, (), self.device, name)
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_graph_capture(self.handle, pos.data_ptr(), mass.data_ptr(), off.ctypes.data,
+                                            len(off) - 1, float(theta), acc.data_ptr(), pot.data_ptr()))
+        self._graph_keep = (pos, mass, acc, pot)
+
+    def graph_launch(self):
+        _check(lib().mibh_graph_launch(self.handle))
+        self.n = int(self._graph_keep[0].shape[0])
+        self._out = self._graph_keep[2:]
+
     def compute_multipoles(self):
         _check(lib().mibh_compute_multipoles(self.handle))
 
@@ -245,12 +293,12 @@ class Decoded:
         import numpy as np
         a = t.cpu().numpy().view(np.uint32).reshape(-1, 4)
         return {"first": a[:, 0].astype(np.int64), "count": a[:, 1].astype(np.int64),
-                "child_first": a[:, 2].astype(np.int64), "level": (a[:, 3] >> 8).astype(np.int32),
-                "nchild": (a[:, 3] & 255).astype(np.int32)}
+                "child_first": a[:, 2].astype(np.int64), "level": ((a[:, 3] >> 8) & 255).astype(np.int32),
+                "nchild": (a[:, 3] & 255).astype(np.int32), "system": (a[:, 3] >> 16).astype(np.int32)}
 
     @staticmethod
     def groups(t):
         import numpy as np
         a = t.cpu().numpy().view(np.uint32).reshape(-1, 2)
         return {"first": a[:, 0].astype(np.int64), "count": (a[:, 1] & 255).astype(np.int64),
-                "level": (a[:, 1] >> 8).astype(np.int32)}
+                "level": ((a[:, 1] >> 8) & 255).astype(np.int32), "system": (a[:, 1] >> 16).astype(np.int32)}

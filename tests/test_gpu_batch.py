@@ -1,0 +1,153 @@
+"""Batched ensembles and graph-captured steps on the GPU.
+
+Every system of a batch must reproduce its standalone oracle run: keys,
+permutation, cells, groups and interaction counts bit for bit, forces within
+1e-5 at p99.  A graph-captured step must give the eager step's results bit
+for bit on every replay.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import TOL_P99, gpu_context, p99, rel_err
+from paper_1204_2280_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ensemble(sizes, seed=40):
+    parts_p, parts_m = [], []
+    for k, n in enumerate(sizes):
+        if n == 1:
+            p, m = np.array([[0.5, -0.25, 2.0]], np.float32), np.array([1.0], np.float32)
+        elif k % 2 == 0:
+            p, _, m = W.plummer(n, seed + k, with_velocities=False)
+        else:
+            p, m = W.hernquist(n, seed + k)
+            p = p + np.float32(3.0 * k)  # systems need not overlap or share a cube
+        parts_p.append(p)
+        parts_m.append(m)
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    return np.ascontiguousarray(np.concatenate(parts_p)), np.ascontiguousarray(np.concatenate(parts_m)), off
+
+
+def _run(ctx, pos, mass, off, theta):
+    import torch
+    from paper_1204_2280_amd.mibh import Decoded
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    acc, pot = ctx.forces_batch(p, m, off, theta)
+    ctx.sync()
+    out = {"acc": acc.cpu().numpy().astype(np.float64), "pot": pot.cpu().numpy().astype(np.float64),
+           "keys": ctx.export("keys").cpu().numpy().view(np.uint64),
+           "perm": ctx.export("perm").cpu().numpy().view(np.uint32).astype(np.int64),
+           "cells": Decoded.cells(ctx.export("cells")), "groups": Decoded.groups(ctx.export("groups")),
+           "counts": ctx.export("counts").cpu().numpy().view(np.uint32).astype(np.int64)}
+    return out
+
+
+@pytest.mark.parametrize("theta", [0.75, 0.5])
+def test_batch_systems_match_standalone_oracle(orc, theta):
+    sizes = [5000, 1, 12000, 777, 64, 65, 20000, 3001, 2, 9000]
+    pos, mass, off = _ensemble(sizes)
+    print(f"[gpu] batch of {len(sizes)} systems, n={off[-1]}, theta={theta}", flush=True)
+    ctx = gpu_context(int(off[-1]), max_systems=16)
+    g = _run(ctx, pos, mass, off, theta)
+    cells, groups = g["cells"], g["groups"]
+    assert ctx.stats()["nsys"] == len(sizes)
+    # level-0 cells are the roots in system order
+    roots = np.nonzero(cells["level"] == 0)[0]
+    np.testing.assert_array_equal(roots, np.arange(len(sizes)))
+    np.testing.assert_array_equal(cells["system"][roots], np.arange(len(sizes)))
+    for s, (a, b) in enumerate(zip(off[:-1], off[1:])):
+        T = orc.Tree(pos[a:b], mass[a:b])
+        T.walk(theta)
+        np.testing.assert_array_equal(g["keys"][a:b], T.keys)
+        np.testing.assert_array_equal(g["perm"][a:b] - a, T.perm)
+        mine = np.nonzero(cells["system"] == s)[0]
+        local = -np.ones(len(cells["first"]), np.int64)
+        local[mine] = np.arange(len(mine))
+        oc = T.cells()
+        np.testing.assert_array_equal(cells["first"][mine] - a, oc["first"])
+        np.testing.assert_array_equal(cells["count"][mine], oc["count"])
+        np.testing.assert_array_equal(cells["level"][mine], oc["level"])
+        np.testing.assert_array_equal(cells["nchild"][mine], oc["nchild"])
+        cf = cells["child_first"][mine]
+        np.testing.assert_array_equal(np.where(cells["nchild"][mine] > 0, local[cf], 0), oc["child_first"])
+        gm = np.nonzero(groups["system"] == s)[0]
+        og = T.groups()
+        np.testing.assert_array_equal(groups["first"][gm] - a, og["first"])
+        np.testing.assert_array_equal(groups["count"][gm], og["count"])
+        np.testing.assert_array_equal(groups["level"][gm], og["level"])
+        npc, npp = T.counts()
+        np.testing.assert_array_equal(g["counts"][gm, 0], npc)
+        np.testing.assert_array_equal(g["counts"][gm, 1], npp)
+        acc, pot = T.forces()
+        if b - a == 1:
+            assert np.all(g["acc"][a:b] == 0) and np.all(g["pot"][a:b] == 0)
+            continue
+        assert p99(rel_err(g["acc"][a:b], acc)) <= TOL_P99
+        assert p99(rel_err(g["pot"][a:b], pot)) <= TOL_P99
+
+
+def test_batch_matches_single_system_runs():
+    """A batch gives each system exactly the results of its own single-system step."""
+    import torch
+    sizes = [3000, 8000, 500]
+    pos, mass, off = _ensemble(sizes, seed=70)
+    ctx = gpu_context(int(off[-1]), max_systems=4)
+    g = _run(ctx, pos, mass, off, 0.75)
+    single = gpu_context(int(max(sizes)))
+    for s, (a, b) in enumerate(zip(off[:-1], off[1:])):
+        p = torch.from_numpy(pos[a:b]).to(single.device)
+        m = torch.from_numpy(mass[a:b]).to(single.device)
+        acc, pot = single.forces(p, m, 0.75)
+        single.sync()
+        np.testing.assert_array_equal(acc.cpu().numpy().astype(np.float64), g["acc"][a:b])
+        np.testing.assert_array_equal(pot.cpu().numpy().astype(np.float64), g["pot"][a:b])
+
+
+def test_graph_replays_equal_eager_step():
+    import torch
+    sizes = [4096, 1000, 7000, 300]
+    pos, mass, off = _ensemble(sizes, seed=90)
+    n = int(off[-1])
+    stream = torch.cuda.Stream()
+    ctx = gpu_context(n, max_systems=4, stream=stream)
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    with torch.cuda.stream(stream):
+        acc_e, pot_e = ctx.forces_batch(p, m, off, 0.75)
+        acc_e, pot_e = acc_e.clone(), pot_e.clone()
+        ctx.sync()
+        acc = torch.zeros((n, 3), dtype=torch.float32, device=ctx.device)
+        pot = torch.zeros((n,), dtype=torch.float32, device=ctx.device)
+        ctx.graph_capture(p, m, off, 0.75, acc, pot)
+        for rep in range(4):
+            acc.zero_()
+            pot.fill_(1.0)
+            ctx.graph_launch()
+            ctx.sync()
+            assert torch.equal(acc, acc_e) and torch.equal(pot, pot_e), f"replay {rep}"
+            # eager work between replays
+            x = torch.randn(1000, device=ctx.device).sum()
+            torch.cuda.synchronize()
+        # inputs updated in place are seen by the next replay
+        p2 = p * 1.5
+        p.copy_(p2)
+        ctx.graph_launch()
+        ctx.sync()
+        acc_e2, pot_e2 = ctx.forces_batch(p, m, off, 0.75)
+        ctx.sync()
+        assert torch.equal(acc, acc_e2) and torch.equal(pot, pot_e2)
+
+
+def test_batch_argument_errors():
+    import torch
+    from paper_1204_2280_amd import mibh
+    ctx = gpu_context(1000, max_systems=4)
+    p = torch.zeros((100, 3), dtype=torch.float32, device=ctx.device)
+    m = torch.ones(100, dtype=torch.float32, device=ctx.device)
+    for bad in ([0, 50, 50, 100], [0, 120], [1, 100], [0, 10, 20, 30, 40, 100]):
+        with pytest.raises((mibh.MibhError, ValueError)):
+            ctx.build_tree_batch(p, m, bad)

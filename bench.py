@@ -88,6 +88,80 @@ def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 2):
     }
 
 
+def bench_variant_kahan(pos, mass, theta, steps, warmup):
+    """Same workload with Kahan-compensated accumulation (plain float32 elsewhere)."""
+    import torch
+    from paper_1204_2280_amd import mibh
+    n = len(mass)
+    dev = torch.device("cuda", 0)
+    p = torch.from_numpy(pos).to(dev)
+    m = torch.from_numpy(mass).to(dev)
+    ctx = mibh.Context(n, device=dev, precision=mibh.KAHAN)
+    for _ in range(warmup):
+        ctx.forces(p, m, theta)
+    ctx.sync()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(ctx.stream)
+    for _ in range(steps):
+        ctx.forces(p, m, theta)
+    b.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    del ctx
+    return {"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3)}
+
+
+def bench_variant_ensemble(theta, steps, warmup, nsys=64, seed=4):
+    """Batched ensemble (uneven N, half Plummer, half Hernquist truncated at 50):
+    one graph-replayed batched step vs one single-system step per system."""
+    import numpy as np
+    import torch
+    from paper_1204_2280_amd import mibh, workloads
+    pos, mass, off = workloads.ensemble(nsys, seed)
+    n = int(off[-1])
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    p = torch.from_numpy(pos).to(dev)
+    m = torch.from_numpy(mass).to(dev)
+    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((n,), dtype=torch.float32, device=dev)
+    ctx = mibh.Context(n, device=dev, stream=stream, max_systems=nsys)
+    with torch.cuda.stream(stream):
+        ctx.graph_capture(p, m, off, theta, acc, pot)
+        for _ in range(warmup):
+            ctx.graph_launch()
+        ctx.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            ctx.graph_launch()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_batch = a.elapsed_time(b) / steps
+        ctx.sync()
+        st = ctx.stats()
+        # the same systems one at a time (eager, one context sized for the largest)
+        single = mibh.Context(int(np.max(np.diff(off))), device=dev, stream=stream)
+        views = [(p[off[k]:off[k + 1]], m[off[k]:off[k + 1]], acc[off[k]:off[k + 1]], pot[off[k]:off[k + 1]])
+                 for k in range(nsys)]
+        for _ in range(warmup):
+            for (pk, mk, ak, qk) in views:
+                single.forces(pk, mk, theta, ak, qk)
+        single.sync()
+        a.record(stream)
+        for _ in range(steps):
+            for (pk, mk, ak, qk) in views:
+                single.forces(pk, mk, theta, ak, qk)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_seq = a.elapsed_time(b) / steps
+    return {"workload": f"ensemble_{nsys}sys_seed{seed}_n{n}_theta{theta:g}", "n": n, "nsys": nsys,
+            "ms_per_step_batched_graph": ms_batch, "particles_per_s_batched_graph": n / (ms_batch * 1e-3),
+            "ms_per_step_sequential": ms_seq, "particles_per_s_sequential": n / (ms_seq * 1e-3),
+            "speedup": ms_seq / ms_batch, "interactions_per_s_batched":
+                (st["sum_pc"] + st["sum_pp"]) / (ms_batch * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +173,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--walk-waves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the Kahan and batched-ensemble variants")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -203,6 +279,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         result["copy_check_bytes"] = nb
+    if not args.no_variants:
+        log("[bench] variant: kahan")
+        result["variant_kahan"] = bench_variant_kahan(pos, mass, theta, max(3, args.steps // 4), 1)
+        log("[bench] variant: batched ensemble")
+        result["variant_ensemble"] = bench_variant_ensemble(theta, max(3, args.steps // 4), 1)
+        log("[bench] variants done")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(pos, mass, theta)

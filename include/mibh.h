@@ -175,11 +175,14 @@ mibh_status mibh_energy(mibh_ctx *ctx, const float *d_vel, double *T, double *W)
  *   MIBH_EXPORT_MAC     float32 [ncells][4] com x y z (float32), r_open^2
  *   MIBH_EXPORT_QUAD    float32 [ncells][8] M, Qxx Qyy Qzz, Qxy Qxz Qyz, 0
  *   MIBH_EXPORT_SPOS    float32 [n][4]    sorted x y z m
+ *   MIBH_EXPORT_FEATURES float32 [ngroups][8] work-estimator features (mibh_group_features)
+ *   MIBH_EXPORT_PREDICTIONS float32 [ngroups] estimator output of the last compute_forces
+ *                                         with MIBH_BALANCE_ESTIMATOR
  * Synchronises (it reads the current sizes).  Errors: EINVAL, ESTATE. */
 enum {
     MIBH_EXPORT_KEYS = 0, MIBH_EXPORT_PERM, MIBH_EXPORT_CELLS, MIBH_EXPORT_GROUPS,
     MIBH_EXPORT_COUNTS, MIBH_EXPORT_MULTIPOLES, MIBH_EXPORT_DELTA, MIBH_EXPORT_MAC,
-    MIBH_EXPORT_QUAD, MIBH_EXPORT_SPOS
+    MIBH_EXPORT_QUAD, MIBH_EXPORT_SPOS, MIBH_EXPORT_FEATURES, MIBH_EXPORT_PREDICTIONS
 };
 mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes);
 mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes);
@@ -198,6 +201,48 @@ enum {
 };
 mibh_status mibh_profile_begin(mibh_ctx *ctx, int max_steps);
 mibh_status mibh_profile_read(mibh_ctx *ctx, float *ms, int max_steps, int *nsteps);
+
+/* Learned work estimator (not part of the paper's method; it never changes
+ * the results, only how the walk's groups are split among its eight queues).
+ * An MLP 8 -> 64 -> 64 -> 1 with ReLU, float16 weights and float32
+ * arithmetic predicts y = log2(1 + n_pc + n_pp) of a group from its features:
+ * log2(count)/6, log2(bounding extent/L)/24, log2(|box centre - system com|/L)/24,
+ * log2(density relative to the system mean)/32, theta, level/20,
+ * log2(system particles)/24, log2(theta)  (L: the system's root cube side).
+ * Weights: MIBH_MLP_PARAMS float16 values, layout W1[64][8], b1[64], W2[64][64],
+ * b2[64], w3[64], b3.  Device pointers; all calls enqueue on `stream`. */
+#define MIBH_MLP_FEATURES 8
+#define MIBH_MLP_PARAMS 4801
+enum { MIBH_BALANCE_EQUAL = 0, MIBH_BALANCE_ESTIMATOR = 1, MIBH_BALANCE_EXACT = 2 };
+
+/* Features of every group of the current tree for this theta into d_feat
+ * [ngroups][8] (NULL: the context's own buffer, see MIBH_EXPORT_FEATURES).
+ * Errors: ESTATE before compute_multipoles, EINVAL. */
+mibh_status mibh_group_features(mibh_ctx *ctx, float theta, float *d_feat);
+
+/* How compute_forces splits the groups (Morton order) into the walk's eight
+ * queues: EQUAL group counts; ESTIMATOR, equal predicted work count*2^y with
+ * the float16 weights d_w16 (kept by pointer); EXACT, equal work from the
+ * exact counts of the previous walk of the same tree (EQUAL when the tree is
+ * new).  Errors: EINVAL. */
+mibh_status mibh_set_balance(mibh_ctx *ctx, int mode, const void *d_w16);
+
+/* y[r] = MLP(x[r]) for rows r < rows (x: float32 [rows][8], y: float32 [rows]). */
+mibh_status mibh_mlp_forward(const void *d_w16, const float *d_x, int64_t rows, float *d_y, void *stream);
+
+/* Gradient of the mean squared error (1/B) sum_b (MLP(x[idx[b]]) - t[idx[b]])^2 over
+ * the B = batch sampled rows idx (int32 [batch]) with respect to the MIBH_MLP_PARAMS
+ * parameters, into d_grad (float32 [4801]); d_loss (float32 [1], nullable) gets the
+ * loss.  d_scratch holds mibh_mlp_scratch_bytes(batch) bytes.  Deterministic. */
+size_t mibh_mlp_scratch_bytes(int batch);
+mibh_status mibh_mlp_gradient(const void *d_w16, const float *d_x, const float *d_t, const int32_t *d_idx,
+                              int batch, float *d_grad, float *d_loss, void *d_scratch, size_t scratch_bytes,
+                              void *stream);
+
+/* One Adam step (step >= 1) on float32 master weights d_w32 with moments d_m,
+ * d_v (all float32 [4801]); writes the float16 copy d_w16. */
+mibh_status mibh_mlp_adam(float *d_w32, void *d_w16, const float *d_grad, float *d_m, float *d_v, int step,
+                          float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Human-readable status name, and the calling thread's last error message. */
 const char *mibh_status_string(mibh_status s);

@@ -17,6 +17,9 @@ struct mibh_ctx {
     mibh_params p;
     int64_t n_max;
     int nsys;                 // systems of the current tree
+    int balance;              // queue split: MIBH_BALANCE_*
+    const void *est_w16;      // estimator weights (float16, caller-owned)
+    int counts_valid;         // gcounts belong to the current tree
     hipGraph_t graph;         // captured step (mibh_graph_capture)
     hipGraphExec_t graph_exec;
     int graph_nsys;
@@ -126,6 +129,9 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.groups = (uint2 *)take(8 * n);
     t.gcounts = (uint2 *)take(8 * n);
     t.wstack = (uint32_t *)take(4 * (size_t)STACK_CAP * waves);
+    t.feat = (float *)take(4 * (size_t)MLP_IN * n);
+    t.pred = (float *)take(4 * n);
+    t.split_chunk = (float *)take(4 * 1024);
     t.epart = (double *)take(8 * 2 * ENERGY_BLOCKS + 16);
     t.cap_cells = (unsigned)cap_cells;
     t.n_max = (unsigned)n_max;
@@ -209,6 +215,9 @@ mibh_status mibh_create(const mibh_params *pp, int64_t n_max, void *d_workspace,
     c->events = nullptr;
     c->prof_max = c->prof_step = 0;
     c->nsys = 1;
+    c->balance = MIBH_BALANCE_EQUAL;
+    c->est_w16 = nullptr;
+    c->counts_valid = 0;
     c->graph = nullptr;
     c->graph_exec = nullptr;
     hipError_t e = hipGetDevice(&c->device);
@@ -285,6 +294,7 @@ mibh_status mibh_build_tree_batch(mibh_ctx *ctx, const float *d_pos, const float
     if ((st = mark(ctx, MIBH_STAGE_BUILD))) return st;
     ctx->n = n;
     ctx->nsys = nsys;
+    ctx->counts_valid = 0;
     ctx->pos = d_pos;
     ctx->mass = d_mass;
     ctx->state = 1;
@@ -316,11 +326,19 @@ mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float 
     if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
     const double inv_theta = 1.0 / (double)theta;
     HIP_TRY(launch_mac_prep(ctx->b, (unsigned)ctx->nsys, inv_theta, ctx->stream), "mac_prep");
+    int mode = ctx->balance;
+    if (mode == MIBH_BALANCE_EXACT && !ctx->counts_valid) mode = MIBH_BALANCE_EQUAL;  // no walk of this tree yet
+    if (mode == MIBH_BALANCE_ESTIMATOR) {
+        HIP_TRY(launch_features(ctx->b, theta, ctx->b.feat, ctx->stream), "features");
+        HIP_TRY(launch_mlp_forward(ctx->est_w16, ctx->b.feat, 0, ctx->b.hdr, ctx->b.pred, ctx->stream), "estimator");
+    }
+    HIP_TRY(launch_queue_split(ctx->b, mode, ctx->stream), "queue split");
     if ((st = mark(ctx, MIBH_STAGE_MACPREP))) return st;
     HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, (unsigned)ctx->nsys, ctx->p.eps2, ctx->p.G, ctx->p.precision,
                         d_acc, d_pot, ctx->stream),
             "walk");
     if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;
+    ctx->counts_valid = 1;
     if (ctx->events && ctx->prof_step < ctx->prof_max) ctx->prof_step++;
     ctx->acc = d_acc;
     ctx->pot = d_pot;
@@ -435,6 +453,8 @@ mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes) {
         case MIBH_EXPORT_MAC: *bytes = 16 * nc; break;
         case MIBH_EXPORT_QUAD: *bytes = 32 * nc; break;
         case MIBH_EXPORT_SPOS: *bytes = 16 * n; break;
+        case MIBH_EXPORT_FEATURES: *bytes = 4 * (size_t)MLP_IN * ng; break;
+        case MIBH_EXPORT_PREDICTIONS: *bytes = 4 * ng; break;
         default: return fail(MIBH_EINVAL, "unknown export %d", what);
     }
     return MIBH_OK;
@@ -463,6 +483,8 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
         case MIBH_EXPORT_MAC: src = ctx->b.cmac; break;
         case MIBH_EXPORT_QUAD: src = ctx->b.ceval; break;
         case MIBH_EXPORT_SPOS: src = ctx->b.spos; break;
+        case MIBH_EXPORT_FEATURES: src = ctx->b.feat; break;
+        case MIBH_EXPORT_PREDICTIONS: src = ctx->b.pred; break;
     }
     if (need) HIP_TRY(hipMemcpyAsync(d_dst, src, need, hipMemcpyDeviceToDevice, ctx->stream), "hipMemcpyAsync(export)");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
@@ -524,6 +546,53 @@ mibh_status mibh_graph_launch(mibh_ctx *ctx) {
     ctx->acc = ctx->graph_acc;
     ctx->pot = ctx->graph_pot;
     ctx->state = 3;
+    return MIBH_OK;
+}
+
+mibh_status mibh_group_features(mibh_ctx *ctx, float theta, float *d_feat) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->state < 2) return fail(MIBH_ESTATE, "features before compute_multipoles");
+    if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
+    HIP_TRY(launch_features(ctx->b, theta, d_feat ? d_feat : ctx->b.feat, ctx->stream), "features");
+    return MIBH_OK;
+}
+
+mibh_status mibh_set_balance(mibh_ctx *ctx, int mode, const void *d_w16) {
+    if (!ctx) return fail(MIBH_EINVAL, "null context");
+    if (mode < MIBH_BALANCE_EQUAL || mode > MIBH_BALANCE_EXACT) return fail(MIBH_EINVAL, "unknown balance mode");
+    if (mode == MIBH_BALANCE_ESTIMATOR && !d_w16) return fail(MIBH_EINVAL, "estimator weights needed");
+    ctx->balance = mode;
+    ctx->est_w16 = d_w16;
+    return MIBH_OK;
+}
+
+mibh_status mibh_mlp_forward(const void *d_w16, const float *d_x, int64_t rows, float *d_y, void *stream) {
+    if (!d_w16 || !d_x || !d_y) return fail(MIBH_EINVAL, "null pointer");
+    if (rows < 1 || rows >= ((int64_t)1 << 31)) return fail(MIBH_EINVAL, "rows out of range");
+    HIP_TRY(launch_mlp_forward(d_w16, d_x, (unsigned)rows, nullptr, d_y, (hipStream_t)stream), "mlp_forward");
+    return MIBH_OK;
+}
+
+size_t mibh_mlp_scratch_bytes(int batch) { return batch < 1 ? 0 : mlp_scratch_bytes((unsigned)batch); }
+
+mibh_status mibh_mlp_gradient(const void *d_w16, const float *d_x, const float *d_t, const int32_t *d_idx, int batch,
+                              float *d_grad, float *d_loss, void *d_scratch, size_t scratch_bytes, void *stream) {
+    if (!d_w16 || !d_x || !d_t || !d_idx || !d_grad || !d_scratch) return fail(MIBH_EINVAL, "null pointer");
+    if (batch < 1 || batch > (1 << 24)) return fail(MIBH_EINVAL, "batch out of range");
+    if (scratch_bytes < mlp_scratch_bytes((unsigned)batch)) return fail(MIBH_ENOMEM, "scratch too small");
+    HIP_TRY(launch_mlp_grad(d_w16, d_x, d_t, d_idx, (unsigned)batch, d_grad, d_loss, d_scratch, (hipStream_t)stream),
+            "mlp_gradient");
+    return MIBH_OK;
+}
+
+mibh_status mibh_mlp_adam(float *d_w32, void *d_w16, const float *d_grad, float *d_m, float *d_v, int step, float lr,
+                          float beta1, float beta2, float eps, void *stream) {
+    if (!d_w32 || !d_w16 || !d_grad || !d_m || !d_v) return fail(MIBH_EINVAL, "null pointer");
+    if (step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return fail(MIBH_EINVAL, "invalid Adam hyper-parameters");
+    HIP_TRY(launch_adam(d_w32, d_w16, d_grad, d_m, d_v, step, lr, beta1, beta2, eps, (hipStream_t)stream), "adam");
     return MIBH_OK;
 }
 

@@ -41,6 +41,8 @@ struct SysCube {
 };
 
 constexpr int MAX_SYSTEMS = 256;        // systems per batch (one extra 8-bit sort pass)
+constexpr int MLP_IN = 8, MLP_H = 64;   // work estimator 8 -> 64 -> 64 -> 1
+constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 4801
 constexpr int BBOX_MIN_BLOCKS = 16;     // bounding-box blocks per system at least
 
 // Device-resident per-context state, rewritten by every build.
@@ -51,6 +53,7 @@ struct Header {
     unsigned ncells;
     unsigned ngroups;
     unsigned walk_next[8];  // persistent walk: head of each of the 8 group queues (one per XCD)
+    unsigned qbeg[9];       // queue q holds groups [qbeg[q], qbeg[q+1])
     unsigned lvl_begin[24]; // cells of level l are [lvl_begin[l], lvl_begin[l+1]), l = 0..20
     unsigned long long sum_pc, sum_pp;
     unsigned pad[8];
@@ -85,6 +88,9 @@ struct Buffers {
     uint2 *groups;          // first, system<<16 | level<<8 | count
     uint2 *gcounts;         // n_pc, n_pp
     uint32_t *wstack;       // per walk wave: STACK_CAP (spill of the LDS stack)
+    float *feat;            // work estimator: group features [n][8]
+    float *pred;            // work estimator: predicted log2(1 + n_pc + n_pp) per group
+    float *split_chunk;     // work of 1024 consecutive group chunks (queue split)
     double *epart;          // energy partials [ENERGY_BLOCKS][2]
     unsigned cap_cells, n_max, ntiles_max, nblk_max;
     unsigned walk_waves, pc_cap, pp_cap, max_systems;
@@ -114,6 +120,16 @@ hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s);
 hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double inv_theta, hipStream_t s);
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
                        float *acc, float *pot, hipStream_t s);
+hipError_t launch_features(const Buffers &b, float theta, float *feat, hipStream_t s);
+hipError_t launch_mlp_forward(const void *w16, const float *x, unsigned rows, const Header *hdr, float *y,
+                              hipStream_t s);
+size_t mlp_scratch_bytes(unsigned batch);
+hipError_t launch_mlp_grad(const void *w16, const float *x, const float *target, const int *idx, unsigned batch,
+                           float *grad, float *loss, void *scratch, hipStream_t s);
+hipError_t launch_adam(float *w32, void *w16, const float *grad, float *m, float *v, int step, float lr,
+                       float beta1, float beta2, float eps, hipStream_t s);
+// mode 0: equal group counts, 1: estimator predictions, 2: exact counts of the last walk
+hipError_t launch_queue_split(const Buffers &b, int mode, hipStream_t s);
 hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
                          unsigned n, double *d_out2, hipStream_t s);
 

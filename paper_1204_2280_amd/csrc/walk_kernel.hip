@@ -3,8 +3,9 @@
 //
 // One wave64 per group (the vector-machine idea of Barnes 1990: one
 // interaction list shared by a group of nearby particles), persistent waves
-// pulling groups from eight device-side queues: queue q holds the q-th eighth
-// of the groups in Morton order and is served first by the waves of XCD q
+// pulling groups from eight device-side queues: queue q holds a contiguous
+// eighth of the groups in Morton order (equal group counts, or equal predicted
+// or measured work) and is served first by the waves of XCD q
 // (workgroups are dispatched to the 8 XCDs round-robin), so the concurrent
 // groups of one XCD are spatial neighbours sharing most of their cells in that
 // XCD's L2.  A wave whose queue is empty steals from the next one.
@@ -239,14 +240,12 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
     const unsigned ln = lane64();
     uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
     if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
-    const unsigned ngroups = a.hdr->ngroups;
     // particles a lane may add to the particle-particle list per round, so that
     // a round (<= 64 * per_round) fits after a flush leaves < 64 entries
     const unsigned per_round = max(1u, (a.pp_cap - 64u) >> 6);
     unsigned q = blockIdx.x & 7u, exhausted = 0;
     for (;;) {
-        const unsigned qb = (unsigned)(((unsigned long long)ngroups * q) >> 3);
-        const unsigned qe = (unsigned)(((unsigned long long)ngroups * (q + 1)) >> 3);
+        const unsigned qb = a.hdr->qbeg[q], qe = a.hdr->qbeg[q + 1];
         // Every lane executes the queue atomic (only lane 0 adds 1) so that no
         // lane-dependent branch sits inside this loop: the compiler may split a
         // loop on a loop-invariant divergent condition, which would separate

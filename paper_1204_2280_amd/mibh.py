@@ -21,8 +21,10 @@ LIB_PATH = os.path.join(HERE, "libmibh.so")
 PLAIN, KAHAN = 0, 1
 EXPORTS = {
     "keys": 0, "perm": 1, "cells": 2, "groups": 3, "counts": 4, "multipoles": 5, "delta": 6,
-    "mac": 7, "quad": 8, "spos": 9,
+    "mac": 7, "quad": 8, "spos": 9, "features": 10, "predictions": 11,
 }
+BALANCE_EQUAL, BALANCE_ESTIMATOR, BALANCE_EXACT = 0, 1, 2
+MLP_FEATURES, MLP_PARAMS = 8, 4801
 STAGES = ("sorting", "moving", "tree_construction", "multipoles", "mac_prep", "walk")
 STATUS = {0: "MIBH_OK", -1: "MIBH_EINVAL", -2: "MIBH_ENOMEM", -3: "MIBH_EHIP", -4: "MIBH_ESTATE",
           -5: "MIBH_EOVERFLOW", -6: "MIBH_ENONFINITE"}
@@ -80,6 +82,16 @@ def lib():
                   "mibh_graph_capture", "mibh_graph_launch", "mibh_set_stream", "mibh_compute_multipoles",
                   "mibh_compute_forces", "mibh_forces", "mibh_sync", "mibh_stats", "mibh_energy",
                   "mibh_export_bytes", "mibh_export"):
+            getattr(L, f).restype = st
+        L.mibh_group_features.argtypes = [P, C.c_float, P]
+        L.mibh_set_balance.argtypes = [P, C.c_int, P]
+        L.mibh_mlp_forward.argtypes = [P, P, i64, P, P]
+        L.mibh_mlp_scratch_bytes.argtypes = [C.c_int]
+        L.mibh_mlp_scratch_bytes.restype = C.c_size_t
+        L.mibh_mlp_gradient.argtypes = [P, P, P, P, C.c_int, P, P, P, C.c_size_t, P]
+        L.mibh_mlp_adam.argtypes = [P, P, P, P, P, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, P]
+        for f in ("mibh_group_features", "mibh_set_balance", "mibh_mlp_forward", "mibh_mlp_gradient",
+                  "mibh_mlp_adam"):
             getattr(L, f).restype = st
         L.mibh_profile_begin.argtypes = [P, C.c_int]
         L.mibh_profile_read.argtypes = [P, P, C.c_int, C.POINTER(C.c_int)]
@@ -254,6 +266,16 @@ class Context:
         _check(lib().mibh_energy(self.handle, _ptr(vel), C.byref(T), C.byref(W)))
         return T.value, W.value
 
+    def group_features(self, theta: float):
+        """Work-estimator features of the current tree's groups, float32 [ngroups, 8]."""
+        _check(lib().mibh_group_features(self.handle, float(theta), None))
+        return self.export("features")
+
+    def set_balance(self, mode: int, w16=None):
+        """Queue split of the walk: BALANCE_EQUAL, BALANCE_ESTIMATOR (float16 weights) or BALANCE_EXACT."""
+        _check(lib().mibh_set_balance(self.handle, int(mode), None if w16 is None else w16.data_ptr()))
+        self._est = w16
+
     def profile_begin(self, max_steps: int):
         """Record stage events for the next max_steps steps."""
         _check(lib().mibh_profile_begin(self.handle, max_steps))
@@ -280,8 +302,47 @@ class Context:
                 "groups": (torch.int32, (-1, 2)), "counts": (torch.int32, (-1, 2)),
                 "multipoles": (torch.float64, (-1, 10)), "delta": (torch.float64, (-1,)),
                 "mac": (torch.float32, (-1, 4)), "quad": (torch.float32, (-1, 8)),
-                "spos": (torch.float32, (-1, 4))}[what]
+                "spos": (torch.float32, (-1, 4)), "features": (torch.float32, (-1, MLP_FEATURES)),
+                "predictions": (torch.float32, (-1,))}[what]
         return buf.view(view[0]).reshape(view[1])
+
+
+def _stream_ptr(t):
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def mlp_forward(w16, x, y=None):
+    """y = MLP(x) for x float32 [rows, 8] with float16 weights [4801]."""
+    import torch
+    rows = int(x.shape[0])
+    if y is None:
+        y = torch.empty(rows, dtype=torch.float32, device=x.device)
+    _check(lib().mibh_mlp_forward(w16.data_ptr(), x.data_ptr(), rows, y.data_ptr(), _stream_ptr(x)))
+    return y
+
+
+def mlp_gradient(w16, x, t, idx, grad=None, loss=None, scratch=None):
+    """Gradient of the batch mean squared error; returns (grad float32 [4801], loss float32 [1])."""
+    import torch
+    dev = x.device
+    batch = int(idx.shape[0])
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nb = int(lib().mibh_mlp_scratch_bytes(batch))
+    if scratch is None or scratch.numel() < nb:
+        scratch = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib().mibh_mlp_gradient(w16.data_ptr(), x.data_ptr(), t.data_ptr(), idx.data_ptr(), batch,
+                                   grad.data_ptr(), loss.data_ptr(), scratch.data_ptr(), scratch.numel(),
+                                   _stream_ptr(x)))
+    return grad, loss
+
+
+def mlp_adam(w32, w16, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().mibh_mlp_adam(w32.data_ptr(), w16.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                               int(step), float(lr), float(beta1), float(beta2), float(eps), _stream_ptr(w32)))
 
 
 @dataclass

@@ -1,0 +1,135 @@
+"""Learned work estimator on the GPU: kernels vs the float64 reference,
+training, and its use in the walk (results unchanged, balance improved)."""
+import numpy as np
+import pytest
+
+import mlp_reference as R
+from gpu_helpers import gpu_context
+from paper_1204_2280_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_forward_and_gradient_match_reference():
+    torch = _torch()
+    from paper_1204_2280_amd import mibh
+    rng = np.random.default_rng(5)
+    w = (rng.standard_normal(R.NPARAM) * 0.2).astype(np.float16)
+    wr = w.astype(np.float64)  # the reference uses the same float16-rounded weights
+    x = rng.standard_normal((1000, 8)).astype(np.float32)
+    t = rng.standard_normal(1000).astype(np.float32)
+    dev = torch.device("cuda", 0)
+    w16 = torch.from_numpy(w).to(dev)
+    xg = torch.from_numpy(x).to(dev)
+    tg = torch.from_numpy(t).to(dev)
+    y = mibh.mlp_forward(w16, xg).cpu().numpy().astype(np.float64)
+    yr, _ = R.forward(wr, x.astype(np.float64))
+    np.testing.assert_allclose(y, yr, rtol=1e-5, atol=1e-5 * np.abs(yr).max())
+    idx = rng.choice(1000, 777, replace=True).astype(np.int32)
+    grad, loss = mibh.mlp_gradient(w16, xg, tg, torch.from_numpy(idx).to(dev))
+    g = grad.cpu().numpy().astype(np.float64)
+    gr = R.gradient(wr, x[idx].astype(np.float64), t[idx].astype(np.float64))
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+    assert abs(float(loss.item()) - R.loss(wr, x[idx], t[idx])) <= 1e-4 * R.loss(wr, x[idx], t[idx])
+    # deterministic
+    grad2, _ = mibh.mlp_gradient(w16, xg, tg, torch.from_numpy(idx).to(dev))
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_step_matches_reference():
+    torch = _torch()
+    from paper_1204_2280_amd import mibh
+    rng = np.random.default_rng(6)
+    dev = torch.device("cuda", 0)
+    w = rng.standard_normal(R.NPARAM).astype(np.float32)
+    g = rng.standard_normal(R.NPARAM).astype(np.float32)
+    m = rng.standard_normal(R.NPARAM).astype(np.float32) * 0.1
+    v = np.abs(rng.standard_normal(R.NPARAM)).astype(np.float32) * 0.1
+    w32, g32, m32, v32 = (torch.from_numpy(a.copy()).to(dev) for a in (w, g, m, v))
+    w16 = torch.empty(R.NPARAM, dtype=torch.float16, device=dev)
+    mibh.mlp_adam(w32, w16, g32, m32, v32, 3, 1e-2)
+    wr, mr, vr = R.adam(w.astype(np.float64), g.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                        3, 1e-2)
+    np.testing.assert_allclose(w32.cpu().numpy(), wr, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(m32.cpu().numpy(), mr, rtol=1e-5, atol=1e-7)
+    np.testing.assert_array_equal(w16.cpu().numpy(), w32.cpu().numpy().astype(np.float16))
+
+
+def _walk_data(ctx, pos, mass, theta):
+    torch = _torch()
+    from paper_1204_2280_amd import estimator
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    ctx.forces(p, m, theta)
+    ctx.sync()
+    return estimator.collect(ctx, theta)
+
+
+def test_training_learns_interaction_counts():
+    torch = _torch()
+    from paper_1204_2280_amd import estimator
+    ctx = gpu_context(1 << 18)
+    xs, ts = [], []
+    for seed, n, theta in ((1, 1 << 15, 0.75), (2, 1 << 17, 0.5), (3, 1 << 18, 1.0), (4, 1 << 16, 0.75)):
+        pos, _, mass = W.plummer(n, seed, with_velocities=False)
+        x, t = _walk_data(ctx, pos, mass, theta)
+        xs.append(x)
+        ts.append(t)
+    x, t = torch.cat(xs), torch.cat(ts)
+    w32, w16, losses = estimator.train(x, t, steps=800, batch=1024, lr=3e-3)
+    print(f"[gpu] estimator losses {losses[0]} -> {losses[-1]}", flush=True)
+    assert losses[-1][1] < 0.1 * losses[0][1]
+    # held-out system
+    pos, _, mass = W.plummer(1 << 17, 9, with_velocities=False)
+    xh, th = _walk_data(ctx, pos, mass, 0.75)
+    q = estimator.evaluate(w16, xh, th)
+    print(f"[gpu] held-out estimator quality {q}", flush=True)
+    assert q["rms_log2"] < 0.35 and q["mape"] < 0.3
+
+
+def test_balance_modes_change_nothing_but_the_split():
+    """Equal, estimator (trained or all-zero) and exact splits give bit-identical
+    counts and forces; the estimator split is closer to equal work per queue."""
+    torch = _torch()
+    from paper_1204_2280_amd import estimator, mibh
+    pos, mass = W.two_plummers(1 << 16)
+    ctx = gpu_context(len(mass))
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    x, t = _walk_data(ctx, pos, mass, 0.75)
+    w32, w16, _ = estimator.train(x, t, steps=400, batch=1024, lr=3e-3)
+    zero16 = torch.zeros(mibh.MLP_PARAMS, dtype=torch.float16, device=ctx.device)
+    ref = None
+    works = {}
+    counts = ctx.export("counts").view(torch.int32).reshape(-1, 2).cpu().numpy().astype(np.int64)
+    gn = mibh.Decoded.groups(ctx.export("groups"))["count"]
+    work = gn * (1 + counts[:, 0] + counts[:, 1])
+    for mode, w in ((mibh.BALANCE_EQUAL, None), (mibh.BALANCE_ESTIMATOR, w16), (mibh.BALANCE_ESTIMATOR, zero16),
+                    (mibh.BALANCE_EXACT, None)):
+        ctx.set_balance(mode, w)
+        acc, pot = ctx.forces(p, m, 0.75)
+        if mode == mibh.BALANCE_EXACT:
+            acc, pot = ctx.compute_forces(0.75)  # a second walk of the same tree has exact counts
+        ctx.sync()
+        c = ctx.export("counts").view(torch.int32).cpu().numpy()
+        got = (acc.cpu().numpy(), pot.cpu().numpy(), c)
+        if ref is None:
+            ref = got
+        for a, b in zip(ref, got):
+            np.testing.assert_array_equal(a, b)
+        if mode == mibh.BALANCE_ESTIMATOR and w is w16:
+            pred = ctx.export("predictions").cpu().numpy().astype(np.float64)
+            pw = gn * np.exp2(np.clip(pred, 0, 40))
+            cut = np.searchsorted(np.cumsum(pw), np.sum(pw) * np.arange(1, 8) / 8.0)
+            works["estimator"] = [int(s.sum()) for s in np.split(work, cut)]
+    eq = [int(s.sum()) for s in np.array_split(work, 8)]
+    imb_eq = max(eq) / np.mean(eq)
+    imb_est = max(works["estimator"]) / np.mean(works["estimator"])
+    print(f"[gpu] queue work max/mean: equal split {imb_eq:.3f}, estimator split {imb_est:.3f}", flush=True)
+    assert imb_est <= imb_eq

@@ -155,7 +155,23 @@ def bench_variant_ensemble(theta, steps, warmup, nsys=64, seed=4):
         b.record(stream)
         torch.cuda.synchronize()
         ms_seq = a.elapsed_time(b) / steps
+        # autotuned parameters (ncrit, group size, walk waves), graph-replayed
+        from paper_1204_2280_amd import autotune
+        best, cands = autotune.tune(p, m, off, theta, steps=2, warmup=1, max_rel_diff=2e-3, use_cache=False,
+                                    write_cache=False)
+        tuned = mibh.Context(n, device=dev, stream=stream, max_systems=nsys, **best)
+        tuned.graph_capture(p, m, off, theta, acc, pot)
+        tuned.graph_launch()
+        tuned.sync()
+        a.record(stream)
+        for _ in range(steps):
+            tuned.graph_launch()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_tuned = a.elapsed_time(b) / steps
     return {"workload": f"ensemble_{nsys}sys_seed{seed}_n{n}_theta{theta:g}", "n": n, "nsys": nsys,
+            "autotuned": best, "ms_per_step_tuned_graph": ms_tuned,
+            "particles_per_s_tuned_graph": n / (ms_tuned * 1e-3),
             "ms_per_step_batched_graph": ms_batch, "particles_per_s_batched_graph": n / (ms_batch * 1e-3),
             "ms_per_step_sequential": ms_seq, "particles_per_s_sequential": n / (ms_seq * 1e-3),
             "speedup": ms_seq / ms_batch, "interactions_per_s_batched":

@@ -173,10 +173,17 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist
                         const float u = RQR * r5;
                         // a = -M R/r^3 + Q R/r^5 - (5/2)(RQR) R/r^7 ; phi = -(M/r + RQR/(2 r^5))
                         const float coef = fmaf(2.5f * u, rinv2, Mr3);
-                        add<KAHAN>(v[4 * ii + 0], cv[4 * ii + 0], fmaf(QRx, r5, -coef * Rx));
-                        add<KAHAN>(v[4 * ii + 1], cv[4 * ii + 1], fmaf(QRy, r5, -coef * Ry));
-                        add<KAHAN>(v[4 * ii + 2], cv[4 * ii + 2], fmaf(QRz, r5, -coef * Rz));
-                        add<KAHAN>(v[4 * ii + 3], cv[4 * ii + 3], -fmaf(0.5f, u, q0.x * rinv));
+                        if (KAHAN) {
+                            add<true>(v[4 * ii + 0], cv[4 * ii + 0], fmaf(QRx, r5, -coef * Rx));
+                            add<true>(v[4 * ii + 1], cv[4 * ii + 1], fmaf(QRy, r5, -coef * Ry));
+                            add<true>(v[4 * ii + 2], cv[4 * ii + 2], fmaf(QRz, r5, -coef * Rz));
+                            add<true>(v[4 * ii + 3], cv[4 * ii + 3], -fmaf(0.5f, u, q0.x * rinv));
+                        } else {  // the term goes into the sum as two fused multiply-adds
+                            v[4 * ii + 0] = fmaf(-coef, Rx, fmaf(QRx, r5, v[4 * ii + 0]));
+                            v[4 * ii + 1] = fmaf(-coef, Ry, fmaf(QRy, r5, v[4 * ii + 1]));
+                            v[4 * ii + 2] = fmaf(-coef, Rz, fmaf(QRz, r5, v[4 * ii + 2]));
+                            v[4 * ii + 3] = fmaf(-q0.x, rinv, fmaf(-0.5f, u, v[4 * ii + 3]));
+                        }
                     }
                 }
             } else {

@@ -44,28 +44,47 @@ __device__ __forceinline__ unsigned rank_below(unsigned long long mask) {
 
 __device__ __forceinline__ unsigned uniform(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ unsigned wave_excl_scan(unsigned v, unsigned *total) {
-    unsigned x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned y = __shfl_up(x, o, 64);
-        if (lane64() >= (unsigned)o) x += y;
-    }
-    *total = uniform(__shfl(x, 63, 64));
-    return x - v;
-}
-
 __device__ __forceinline__ unsigned bitrev6(unsigned l) {
     return ((l & 1u) << 5) | ((l & 2u) << 3) | ((l & 4u) << 1) | ((l & 8u) >> 1) | ((l & 16u) >> 3) |
            ((l & 32u) >> 5);
 }
 
+// Exclusive prefix sum over the wave of small per-lane values (0 <= v < 16),
+// from four ballots; *total gets the wave total.
+__device__ __forceinline__ unsigned small_excl_scan(unsigned v, unsigned *total) {
+    unsigned r = 0, t = 0;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        const unsigned long long m = __ballot((v >> b) & 1u);
+        r += rank_below(m) << b;
+        t += (unsigned)__popcll(m) << b;
+    }
+    *total = t;
+    return r;
+}
+
 // Sums each of the 64 per-lane values v[0..63] over the wave; lane l gets the
-// total of v[bitrev6(l)].
+// total of v[bitrev6(l)].  Stage with offset o pairs v[2p], v[2p+1]: lanes
+// whose bit o is clear keep the pair sum of v[2p], the others of v[2p+1].  The
+// offsets 32 and 16 are the gfx950 half/row swaps (v_permlane32_swap exchanges
+// the upper half of its first operand with the lower half of its second, so one
+// swap and one add finish a pair); the others use shuffles.
 __device__ __forceinline__ float transpose_reduce(float (&v)[64]) {
     const unsigned ln = lane64();
 #pragma unroll
-    for (int s = 0; s < 6; s++) {
+    for (int p = 0; p < 32; p++) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * p]), __float_as_uint(v[2 * p + 1]),
+                                                        false, false);
+        v[p] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int p = 0; p < 16; p++) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[2 * p]), __float_as_uint(v[2 * p + 1]),
+                                                        false, false);
+        v[p] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int s = 2; s < 6; s++) {
         const int o = 32 >> s;
         const int len = 64 >> s;
         const bool hi = (ln & (unsigned)o) != 0;
@@ -249,7 +268,8 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
     if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
     // particles a lane may add to the particle-particle list per round, so that
     // a round (<= 64 * per_round) fits after a flush leaves < 64 entries
-    const unsigned per_round = max(1u, (a.pp_cap - 64u) >> 6);
+    const unsigned per_round = max(1u, (a.pp_cap - 64u) >> 6);  // < 16 since pp_cap <= 1024
+    static_assert(WALK_PP_LDS <= 1024, "per-round counts must fit the 4-bit prefix sums");
     unsigned q = blockIdx.x & 7u, exhausted = 0;
     for (;;) {
         const unsigned qb = a.hdr->qbeg[q], qe = a.hdr->qbeg[q + 1];
@@ -325,7 +345,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             while (__ballot(rem > 0)) {
                 const unsigned take = min(rem, per_round);
                 unsigned sum;
-                const unsigned off = wave_excl_scan(take, &sum);
+                const unsigned off = small_excl_scan(take, &sum);
                 if (npp + sum > a.pp_cap)
                     npp = flush_list<KAHAN, false>(a, s_pp, npp, false, gn, p.x, p.y, p.z, s_res, s_cmp);
                 for (unsigned j = 0; j < take; j++) s_pp[npp + off + j] = src + j;
@@ -338,7 +358,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             // opened internal cells -> children onto the stack
             unsigned nsum;
             const unsigned nc = push ? nch : 0u;
-            const unsigned off = wave_excl_scan(nc, &nsum);
+            const unsigned off = small_excl_scan(nc, &nsum);
             const unsigned used = st - sb;
             if (used + nsum > WALK_LSTACK) {  // spill the bottom of the LDS ring
                 const unsigned need = used + nsum - WALK_LSTACK;

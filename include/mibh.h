@@ -177,12 +177,14 @@ mibh_status mibh_energy(mibh_ctx *ctx, const float *d_vel, double *T, double *W)
  *   MIBH_EXPORT_SPOS    float32 [n][4]    sorted x y z m
  *   MIBH_EXPORT_FEATURES float32 [ngroups][8] work-estimator features (mibh_group_features)
  *   MIBH_EXPORT_PREDICTIONS float32 [ngroups] estimator output of the last compute_forces
- *                                         with MIBH_BALANCE_ESTIMATOR
+ *                                         with MIBH_ORDER_ESTIMATOR
+ *   MIBH_EXPORT_QUEUE   uint32 [ngroups]  group indices in the order the last walk took them
+ *                                         (ESTATE when that walk used Morton order)
  * Synchronises (it reads the current sizes).  Errors: EINVAL, ESTATE. */
 enum {
     MIBH_EXPORT_KEYS = 0, MIBH_EXPORT_PERM, MIBH_EXPORT_CELLS, MIBH_EXPORT_GROUPS,
     MIBH_EXPORT_COUNTS, MIBH_EXPORT_MULTIPOLES, MIBH_EXPORT_DELTA, MIBH_EXPORT_MAC,
-    MIBH_EXPORT_QUAD, MIBH_EXPORT_SPOS, MIBH_EXPORT_FEATURES, MIBH_EXPORT_PREDICTIONS
+    MIBH_EXPORT_QUAD, MIBH_EXPORT_SPOS, MIBH_EXPORT_FEATURES, MIBH_EXPORT_PREDICTIONS, MIBH_EXPORT_QUEUE
 };
 mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes);
 mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes);
@@ -203,7 +205,8 @@ mibh_status mibh_profile_begin(mibh_ctx *ctx, int max_steps);
 mibh_status mibh_profile_read(mibh_ctx *ctx, float *ms, int max_steps, int *nsteps);
 
 /* Learned work estimator (not part of the paper's method; it never changes
- * the results, only how the walk's groups are split among its eight queues).
+ * the results, only the order in which the walk's persistent waves take the
+ * groups).
  * An MLP 8 -> 64 -> 64 -> 1 with ReLU, float16 weights and float32
  * arithmetic predicts y = log2(1 + n_pc + n_pp) of a group from its features:
  * log2(count)/6, log2(bounding extent/L)/24, log2(|box centre - system com|/L)/24,
@@ -213,19 +216,22 @@ mibh_status mibh_profile_read(mibh_ctx *ctx, float *ms, int max_steps, int *nste
  * b2[64], w3[64], b3.  Device pointers; all calls enqueue on `stream`. */
 #define MIBH_MLP_FEATURES 8
 #define MIBH_MLP_PARAMS 4801
-enum { MIBH_BALANCE_EQUAL = 0, MIBH_BALANCE_ESTIMATOR = 1, MIBH_BALANCE_EXACT = 2 };
+enum { MIBH_ORDER_MORTON = 0, MIBH_ORDER_ESTIMATOR = 1, MIBH_ORDER_EXACT = 2 };
 
 /* Features of every group of the current tree for this theta into d_feat
  * [ngroups][8] (NULL: the context's own buffer, see MIBH_EXPORT_FEATURES).
  * Errors: ESTATE before compute_multipoles, EINVAL. */
 mibh_status mibh_group_features(mibh_ctx *ctx, float theta, float *d_feat);
 
-/* How compute_forces splits the groups (Morton order) into the walk's eight
- * queues: EQUAL group counts; ESTIMATOR, equal predicted work count*2^y with
- * the float16 weights d_w16 (kept by pointer); EXACT, equal work from the
- * exact counts of the previous walk of the same tree (EQUAL when the tree is
- * new).  Errors: EINVAL. */
-mibh_status mibh_set_balance(mibh_ctx *ctx, int mode, const void *d_w16);
+/* Order of the walk's group queue in compute_forces (the default is MORTON).
+ * MORTON: the groups in Morton order.  ESTIMATOR and EXACT: longest
+ * processing time first, a stable counting sort by floor(4 log2 work),
+ * heaviest bucket first and Morton order within a bucket, where work is
+ * count * 2^y predicted with the float16 weights d_w16 (kept by pointer, read
+ * at every compute_forces) or count * (1 + n_pc + n_pp) from the exact counts
+ * of the previous walk of the same tree (MORTON when the tree is new).  The
+ * order never changes the results.  Errors: EINVAL. */
+mibh_status mibh_set_queue_order(mibh_ctx *ctx, int mode, const void *d_w16);
 
 /* y[r] = MLP(x[r]) for rows r < rows (x: float32 [rows][8], y: float32 [rows]). */
 mibh_status mibh_mlp_forward(const void *d_w16, const float *d_x, int64_t rows, float *d_y, void *stream);

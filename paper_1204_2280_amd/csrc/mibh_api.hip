@@ -17,7 +17,8 @@ struct mibh_ctx {
     mibh_params p;
     int64_t n_max;
     int nsys;                 // systems of the current tree
-    int balance;              // queue split: MIBH_BALANCE_*
+    int order;                // walk queue order: MIBH_ORDER_*
+    int last_order;           // order the last walk used (Morton when exact counts were missing)
     const void *est_w16;      // estimator weights (float16, caller-owned)
     int counts_valid;         // gcounts belong to the current tree
     hipGraph_t graph;         // captured step (mibh_graph_capture)
@@ -131,7 +132,8 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.wstack = (uint32_t *)take(4 * (size_t)STACK_CAP * waves);
     t.feat = (float *)take(4 * (size_t)MLP_IN * n);
     t.pred = (float *)take(4 * n);
-    t.split_chunk = (float *)take(4 * 1024);
+    t.qorder = (uint32_t *)take(4 * n);
+    t.ohist = (uint32_t *)take(4 * ORDER_BUCKETS * ORDER_BLOCKS);
     t.epart = (double *)take(8 * 2 * ENERGY_BLOCKS + 16);
     t.cap_cells = (unsigned)cap_cells;
     t.n_max = (unsigned)n_max;
@@ -215,7 +217,7 @@ mibh_status mibh_create(const mibh_params *pp, int64_t n_max, void *d_workspace,
     c->events = nullptr;
     c->prof_max = c->prof_step = 0;
     c->nsys = 1;
-    c->balance = MIBH_BALANCE_EQUAL;
+    c->order = c->last_order = MIBH_ORDER_MORTON;
     c->est_w16 = nullptr;
     c->counts_valid = 0;
     c->graph = nullptr;
@@ -326,17 +328,18 @@ mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float 
     if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
     const double inv_theta = 1.0 / (double)theta;
     HIP_TRY(launch_mac_prep(ctx->b, (unsigned)ctx->nsys, inv_theta, ctx->stream), "mac_prep");
-    int mode = ctx->balance;
-    if (mode == MIBH_BALANCE_EXACT && !ctx->counts_valid) mode = MIBH_BALANCE_EQUAL;  // no walk of this tree yet
-    if (mode == MIBH_BALANCE_ESTIMATOR) {
+    int mode = ctx->order;
+    if (mode == MIBH_ORDER_EXACT && !ctx->counts_valid) mode = MIBH_ORDER_MORTON;  // no walk of this tree yet
+    if (mode == MIBH_ORDER_ESTIMATOR) {
         HIP_TRY(launch_features(ctx->b, theta, ctx->b.feat, ctx->stream), "features");
         HIP_TRY(launch_mlp_forward(ctx->est_w16, ctx->b.feat, 0, ctx->b.hdr, ctx->b.pred, ctx->stream), "estimator");
     }
-    HIP_TRY(launch_queue_split(ctx->b, mode, ctx->stream), "queue split");
+    if (mode != MIBH_ORDER_MORTON) HIP_TRY(launch_queue_order(ctx->b, mode, ctx->stream), "queue order");
     if ((st = mark(ctx, MIBH_STAGE_MACPREP))) return st;
     HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, (unsigned)ctx->nsys, ctx->p.eps2, ctx->p.G, ctx->p.precision,
-                        d_acc, d_pot, ctx->stream),
+                        mode == MIBH_ORDER_MORTON ? nullptr : ctx->b.qorder, d_acc, d_pot, ctx->stream),
             "walk");
+    ctx->last_order = mode;
     if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;
     ctx->counts_valid = 1;
     if (ctx->events && ctx->prof_step < ctx->prof_max) ctx->prof_step++;
@@ -455,6 +458,7 @@ mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes) {
         case MIBH_EXPORT_SPOS: *bytes = 16 * n; break;
         case MIBH_EXPORT_FEATURES: *bytes = 4 * (size_t)MLP_IN * ng; break;
         case MIBH_EXPORT_PREDICTIONS: *bytes = 4 * ng; break;
+        case MIBH_EXPORT_QUEUE: *bytes = 4 * ng; break;
         default: return fail(MIBH_EINVAL, "unknown export %d", what);
     }
     return MIBH_OK;
@@ -466,8 +470,10 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
     if (st) return st;
     if (!d_dst) return fail(MIBH_EINVAL, "null destination");
     if (bytes < need) return fail(MIBH_EINVAL, "destination too small: %zu < %zu", bytes, need);
-    if ((what == MIBH_EXPORT_COUNTS || what == MIBH_EXPORT_MAC) && ctx->state < 3)
+    if ((what == MIBH_EXPORT_COUNTS || what == MIBH_EXPORT_MAC || what == MIBH_EXPORT_QUEUE) && ctx->state < 3)
         return fail(MIBH_ESTATE, "export of walk data before compute_forces");
+    if (what == MIBH_EXPORT_QUEUE && ctx->last_order == MIBH_ORDER_MORTON)
+        return fail(MIBH_ESTATE, "the last walk took the groups in Morton order");
     if ((what == MIBH_EXPORT_MULTIPOLES || what == MIBH_EXPORT_DELTA || what == MIBH_EXPORT_QUAD) &&
         ctx->state < 2)
         return fail(MIBH_ESTATE, "export of multipoles before compute_multipoles");
@@ -485,6 +491,7 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
         case MIBH_EXPORT_SPOS: src = ctx->b.spos; break;
         case MIBH_EXPORT_FEATURES: src = ctx->b.feat; break;
         case MIBH_EXPORT_PREDICTIONS: src = ctx->b.pred; break;
+        case MIBH_EXPORT_QUEUE: src = ctx->b.qorder; break;
     }
     if (need) HIP_TRY(hipMemcpyAsync(d_dst, src, need, hipMemcpyDeviceToDevice, ctx->stream), "hipMemcpyAsync(export)");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
@@ -558,11 +565,11 @@ mibh_status mibh_group_features(mibh_ctx *ctx, float theta, float *d_feat) {
     return MIBH_OK;
 }
 
-mibh_status mibh_set_balance(mibh_ctx *ctx, int mode, const void *d_w16) {
+mibh_status mibh_set_queue_order(mibh_ctx *ctx, int mode, const void *d_w16) {
     if (!ctx) return fail(MIBH_EINVAL, "null context");
-    if (mode < MIBH_BALANCE_EQUAL || mode > MIBH_BALANCE_EXACT) return fail(MIBH_EINVAL, "unknown balance mode");
-    if (mode == MIBH_BALANCE_ESTIMATOR && !d_w16) return fail(MIBH_EINVAL, "estimator weights needed");
-    ctx->balance = mode;
+    if (mode < MIBH_ORDER_MORTON || mode > MIBH_ORDER_EXACT) return fail(MIBH_EINVAL, "unknown queue order %d", mode);
+    if (mode == MIBH_ORDER_ESTIMATOR && !d_w16) return fail(MIBH_EINVAL, "estimator weights needed");
+    ctx->order = mode;
     ctx->est_w16 = d_w16;
     return MIBH_OK;
 }

@@ -52,12 +52,18 @@ struct Header {
     unsigned n;
     unsigned ncells;
     unsigned ngroups;
-    unsigned walk_next[8];  // persistent walk: head of each of the 8 group queues (one per XCD)
-    unsigned qbeg[9];       // queue q holds groups [qbeg[q], qbeg[q+1])
     unsigned lvl_begin[24]; // cells of level l are [lvl_begin[l], lvl_begin[l+1]), l = 0..20
-    unsigned long long sum_pc, sum_pp;
-    unsigned pad[8];
+    // Head of the walk's group queue.  Every wave of the walk increments it, so
+    // it sits on a cache line of its own: sharing a line with the fields above,
+    // which every wave reads, made the walk 1.8 times slower.
+    alignas(256) unsigned walk_head;
+    unsigned pad[63];
 };
+
+// Walk queue order by predicted or measured work: quarter-octave buckets of
+// log2(work), heaviest first, Morton order within a bucket.
+constexpr int ORDER_BUCKETS = 128;
+constexpr int ORDER_BLOCKS = 256;
 
 // Walk: LDS capacities per wave (one wave per workgroup).
 constexpr unsigned WALK_LSTACK = 512;   // cell stack in LDS (spills to the global stack)
@@ -90,7 +96,8 @@ struct Buffers {
     uint32_t *wstack;       // per walk wave: STACK_CAP (spill of the LDS stack)
     float *feat;            // work estimator: group features [n][8]
     float *pred;            // work estimator: predicted log2(1 + n_pc + n_pp) per group
-    float *split_chunk;     // work of 1024 consecutive group chunks (queue split)
+    uint32_t *qorder;       // walk queue: groups in processing order (work-ordered modes)
+    uint32_t *ohist;        // [ORDER_BUCKETS][ORDER_BLOCKS] bucket counts of the queue order
     double *epart;          // energy partials [ENERGY_BLOCKS][2]
     unsigned cap_cells, n_max, ntiles_max, nblk_max;
     unsigned walk_waves, pc_cap, pp_cap, max_systems;
@@ -118,8 +125,9 @@ hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass,
 hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, int gcap, hipStream_t s);
 hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s);
 hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double inv_theta, hipStream_t s);
+// order: the queue (NULL: groups in Morton order)
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
-                       float *acc, float *pot, hipStream_t s);
+                       const uint32_t *order, float *acc, float *pot, hipStream_t s);
 hipError_t launch_features(const Buffers &b, float theta, float *feat, hipStream_t s);
 hipError_t launch_mlp_forward(const void *w16, const float *x, unsigned rows, const Header *hdr, float *y,
                               hipStream_t s);
@@ -128,8 +136,9 @@ hipError_t launch_mlp_grad(const void *w16, const float *x, const float *target,
                            float *grad, float *loss, void *scratch, hipStream_t s);
 hipError_t launch_adam(float *w32, void *w16, const float *grad, float *m, float *v, int step, float lr,
                        float beta1, float beta2, float eps, hipStream_t s);
-// mode 0: equal group counts, 1: estimator predictions, 2: exact counts of the last walk
-hipError_t launch_queue_split(const Buffers &b, int mode, hipStream_t s);
+// Writes b.qorder: the groups ordered by work, heaviest first; mode 1: work
+// predicted by the estimator (b.pred), 2: exact counts of the last walk.
+hipError_t launch_queue_order(const Buffers &b, int mode, hipStream_t s);
 hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
                          unsigned n, double *d_out2, hipStream_t s);
 

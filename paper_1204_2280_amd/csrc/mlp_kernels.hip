@@ -4,8 +4,8 @@
 // stored in float16, arithmetic accumulates in float32.  Training kernels
 // (forward, backward, Adam) run on the GPU; the backward pass is
 // deterministic (per-block outer products summed in a fixed order, then a
-// fixed-order sum over blocks).  The prediction sets the boundaries of the
-// walk's eight XCD queues at equal predicted work.
+// fixed-order sum over blocks).  The prediction orders the walk's group
+// queue, heaviest predicted work first.
 #include "mibh_device.h"
 
 #include <hip/hip_fp16.h>
@@ -221,60 +221,6 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w32, __half *_
     }
 }
 
-// --------------------------------------------------------------------------
-// Queue boundaries of the walk: the groups split into 8 contiguous ranges of
-// equal work, work = count * 2^prediction (or equal group counts without
-// weights).  Chunk sums are taken in a fixed order, so the split is
-// deterministic.
-// --------------------------------------------------------------------------
-
-constexpr int SPLIT_CHUNKS = 1024;
-
-__device__ __forceinline__ float group_work(const uint2 *groups, const float *pred, const uint2 *counts,
-                                            int mode, unsigned g) {
-    const float gn = (float)(groups[g].y & 255u);
-    if (mode == 1) {
-        const float p = pred[g];
-        return isfinite(p) ? gn * exp2f(fminf(fmaxf(p, 0.0f), 40.0f)) : gn;
-    }
-    if (mode == 2) return gn * (float)(1u + counts[g].x + counts[g].y);
-    return 1.0f;
-}
-
-__global__ __launch_bounds__(256) void k_split_sums(const Header *__restrict__ hdr, const uint2 *__restrict__ groups,
-                                                    const float *__restrict__ pred, const uint2 *__restrict__ counts,
-                                                    int mode, float *__restrict__ chunk) {
-    const unsigned ng = hdr->ngroups;
-    const unsigned per = (ng + SPLIT_CHUNKS - 1) / SPLIT_CHUNKS;
-    for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < (unsigned)SPLIT_CHUNKS; c += gridDim.x * 256u) {
-        float a = 0.0f;
-        for (unsigned g = c * per; g < min(ng, (c + 1) * per); g++) a += group_work(groups, pred, counts, mode, g);
-        chunk[c] = a;
-    }
-}
-
-__global__ void k_split_bounds(Header *__restrict__ hdr, const uint2 *__restrict__ groups,
-                               const float *__restrict__ pred, const uint2 *__restrict__ counts, int mode,
-                               const float *__restrict__ chunk) {
-    const unsigned ng = hdr->ngroups;
-    if (threadIdx.x > 8) return;
-    const unsigned q = threadIdx.x;
-    if (mode == 0 || q == 0 || q == 8) {
-        hdr->qbeg[q] = (unsigned)(((unsigned long long)ng * q) >> 3);
-        return;
-    }
-    float total = 0.0f;
-    for (int c = 0; c < SPLIT_CHUNKS; c++) total += chunk[c];
-    const float want = total * (float)q / 8.0f;
-    const unsigned per = (ng + SPLIT_CHUNKS - 1) / SPLIT_CHUNKS;
-    float run = 0.0f;
-    unsigned c = 0;
-    while (c < (unsigned)SPLIT_CHUNKS && run + chunk[c] < want) run += chunk[c++];
-    unsigned g = min(ng, c * per);
-    while (g < ng && run < want) run += group_work(groups, pred, counts, mode, g++);
-    hdr->qbeg[q] = g;
-}
-
 hipError_t launch_features(const Buffers &b, float theta, float *feat, hipStream_t s) {
     const unsigned grid = min((b.n_max + 255u) / 256u, 2048u);
     hipLaunchKernelGGL(k_features, dim3(grid), dim3(256), 0, s, b.hdr, b.cube, b.groups, b.topo, b.spos, b.mp, theta,
@@ -311,14 +257,6 @@ hipError_t launch_adam(float *w32, void *w16, const float *grad, float *m, float
     const float corr1 = 1.0f - powf(beta1, (float)step), corr2 = 1.0f - powf(beta2, (float)step);
     hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, w32, (__half *)w16, grad, m, v, lr,
                        beta1, beta2, eps, corr1, corr2);
-    return hipGetLastError();
-}
-
-hipError_t launch_queue_split(const Buffers &b, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_split_sums, dim3(SPLIT_CHUNKS / 256), dim3(256), 0, s, b.hdr, b.groups, b.pred, b.gcounts,
-                       mode, b.split_chunk);
-    hipLaunchKernelGGL(k_split_bounds, dim3(1), dim3(64), 0, s, b.hdr, b.groups, b.pred, b.gcounts, mode,
-                       b.split_chunk);
     return hipGetLastError();
 }
 

@@ -237,9 +237,7 @@ __global__ void k_header_reset(unsigned n, unsigned nsys, Header *__restrict__ h
         hdr->n = n;
         hdr->ncells = 0;
         hdr->ngroups = 0;
-        for (int q = 0; q < 8; q++) hdr->walk_next[q] = 0;
-        hdr->sum_pc = 0;
-        hdr->sum_pp = 0;
+        hdr->walk_head = 0;
         for (int l = 0; l < 24; l++) hdr->lvl_begin[l] = 0;
     }
 }
@@ -785,7 +783,7 @@ __global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr, cons
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
-    if (blockIdx.x == 0 && threadIdx.x < 8) hdr->walk_next[threadIdx.x] = 0;  // queues of the walk that follows
+    if (blockIdx.x == 0 && threadIdx.x == 0) hdr->walk_head = 0;  // queue of the walk that follows
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
         const unsigned w = topo[c].w;
         const int lev = (int)((w >> 8) & 255u);

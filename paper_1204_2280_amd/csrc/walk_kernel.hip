@@ -3,12 +3,11 @@
 //
 // One wave64 per group (the vector-machine idea of Barnes 1990: one
 // interaction list shared by a group of nearby particles), persistent waves
-// pulling groups from eight device-side queues: queue q holds a contiguous
-// eighth of the groups in Morton order (equal group counts, or equal predicted
-// or measured work) and is served first by the waves of XCD q
-// (workgroups are dispatched to the 8 XCDs round-robin), so the concurrent
-// groups of one XCD are spatial neighbours sharing most of their cells in that
-// XCD's L2.  A wave whose queue is empty steals from the next one.
+// pulling groups from one device-wide queue: an atomic head on a cache line of
+// its own, over the groups in Morton order (concurrent waves then walk
+// spatial neighbours, whose cells are shared in L2) or over a work-ordered
+// permutation, heaviest groups first (longest-processing-time order, which
+// shortens the tail of the persistent grid).
 //
 // Traversal: lanes hold up to 64 candidate cells popped from a per-wave stack
 // kept in LDS (circular, spilling its bottom to a per-wave global stack when
@@ -133,6 +132,8 @@ struct WalkArgs {
     const uint2 *groups;
     uint2 *gcounts;
     uint32_t *wstack;
+    const uint32_t *order;   // queue order (NULL: Morton order)
+    unsigned *head;          // queue head
     float *acc, *pot;
     float eps2, G;
     unsigned pc_cap, pp_cap;
@@ -270,19 +271,15 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
     // a round (<= 64 * per_round) fits after a flush leaves < 64 entries
     const unsigned per_round = max(1u, (a.pp_cap - 64u) >> 6);  // < 16 since pp_cap <= 1024
     static_assert(WALK_PP_LDS <= 1024, "per-round counts must fit the 4-bit prefix sums");
-    unsigned q = blockIdx.x & 7u, exhausted = 0;
+    const unsigned ngroups = uniform(a.hdr->ngroups);
     for (;;) {
-        const unsigned qb = a.hdr->qbeg[q], qe = a.hdr->qbeg[q + 1];
         // Every lane executes the queue atomic (only lane 0 adds 1) so that no
         // lane-dependent branch sits inside this loop: the compiler may split a
         // loop on a loop-invariant divergent condition, which would separate
         // lane 0 from the cross-lane operations of the other lanes.
-        const unsigned g = qb + uniform(atomicAdd(&a.hdr->walk_next[q], ln == 0 ? 1u : 0u));
-        if (g >= qe) {
-            if (++exhausted == 8) break;
-            q = (q + 1) & 7u;
-            continue;
-        }
+        const unsigned slot = uniform(atomicAdd(a.head, ln == 0 ? 1u : 0u));
+        if (slot >= ngroups) break;
+        const unsigned g = a.order ? uniform(a.order[slot]) : slot;
         const uint2 gr = a.groups[g];
         const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform((gr.y >> 8) & 255u);
         const unsigned root = uniform(gr.y >> 16);  // level-0 cells are the systems' roots, in system order
@@ -404,7 +401,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
 }  // namespace
 
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
-                       float *acc, float *pot, hipStream_t s) {
+                       const uint32_t *order, float *acc, float *pot, hipStream_t s) {
     (void)n;
     WalkArgs a;
     a.hdr = b.hdr;
@@ -416,6 +413,8 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
     a.groups = b.groups;
     a.gcounts = b.gcounts;
     a.wstack = b.wstack;
+    a.order = order;
+    a.head = &b.hdr->walk_head;
     a.acc = acc;
     a.pot = pot;
     a.eps2 = eps2;
@@ -426,6 +425,150 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
         hipLaunchKernelGGL(k_walk<true>, dim3(b.walk_waves), dim3(64), 0, s, a);
     else
         hipLaunchKernelGGL(k_walk<false>, dim3(b.walk_waves), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Queue order: a stable counting sort of the groups by work bucket, heaviest
+// bucket first.  work = count * 2^prediction (estimator) or
+// count * (1 + n_pc + n_pp) (exact counts of the last walk); bucket =
+// floor(4 log2 work), clamped to ORDER_BUCKETS values.  Block b owns a
+// contiguous slice of the groups; the blocks' bucket counts, scanned
+// bucket-major (heaviest first) then block-minor, place every group, and ranks
+// inside a block are taken tile by tile in group order, so groups of equal
+// bucket keep their Morton order.  Integer counts only: the order is the same
+// on every run.
+// --------------------------------------------------------------------------
+namespace {
+
+constexpr int ORDER_THREADS = 256;
+constexpr int ORDER_SCAN_THREADS = 1024;
+constexpr unsigned ORDER_SKIP = FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP;  // the walk does nothing then
+
+// Queue bucket of group g: 0 for the heaviest work.
+__device__ __forceinline__ unsigned work_bucket(const uint2 *__restrict__ groups, const float *__restrict__ pred,
+                                                const uint2 *__restrict__ counts, int mode, unsigned g) {
+    const float gn = (float)(groups[g].y & 255u);
+    float l2;
+    if (mode == 1) {
+        const float p = pred[g];
+        l2 = log2f(gn) + (isfinite(p) ? fminf(fmaxf(p, 0.0f), 40.0f) : 0.0f);
+    } else {
+        const uint2 c = counts[g];
+        l2 = log2f(gn * (float)(1u + c.x + c.y));
+    }
+    const int b = min(max((int)floorf(4.0f * l2), 0), ORDER_BUCKETS - 1);
+    return (unsigned)(ORDER_BUCKETS - 1 - b);
+}
+
+__device__ __forceinline__ void order_slice(const Header *hdr, unsigned n_max, unsigned *beg, unsigned *end) {
+    const unsigned ng = min(hdr->ngroups, n_max);
+    const unsigned chunk = (ng + ORDER_BLOCKS - 1) / ORDER_BLOCKS;
+    *beg = min(ng, blockIdx.x * chunk);
+    *end = min(ng, *beg + chunk);
+}
+
+__global__ __launch_bounds__(ORDER_THREADS) void k_order_hist(const Header *__restrict__ hdr, unsigned n_max,
+                                                              const uint2 *__restrict__ groups,
+                                                              const float *__restrict__ pred,
+                                                              const uint2 *__restrict__ counts, int mode,
+                                                              uint32_t *__restrict__ ohist) {
+    __shared__ unsigned s_h[ORDER_BUCKETS];
+    if (hdr->flags & ORDER_SKIP) return;
+    const unsigned t = threadIdx.x;
+    if (t < ORDER_BUCKETS) s_h[t] = 0;
+    __syncthreads();
+    unsigned beg, end;
+    order_slice(hdr, n_max, &beg, &end);
+    for (unsigned g = beg + t; g < end; g += ORDER_THREADS) atomicAdd(&s_h[work_bucket(groups, pred, counts, mode, g)], 1u);
+    __syncthreads();
+    if (t < ORDER_BUCKETS) ohist[t * ORDER_BLOCKS + blockIdx.x] = s_h[t];
+}
+
+// Exclusive prefix sum, in place, of ohist[ORDER_BUCKETS][ORDER_BLOCKS] read
+// as one row-major sequence.
+__global__ __launch_bounds__(ORDER_SCAN_THREADS) void k_order_scan(uint32_t *__restrict__ ohist) {
+    constexpr int PER = ORDER_BUCKETS * ORDER_BLOCKS / ORDER_SCAN_THREADS;
+    static_assert(PER * ORDER_SCAN_THREADS == ORDER_BUCKETS * ORDER_BLOCKS, "scan covers the table");
+    __shared__ unsigned s_w[ORDER_SCAN_THREADS / 64];
+    const unsigned t = threadIdx.x, ln = lane64(), w = t >> 6;
+    unsigned v[PER], sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        v[i] = ohist[t * PER + i];
+        sum += v[i];
+    }
+    unsigned x = sum;  // inclusive scan over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o, 64);
+        x += ln >= (unsigned)o ? y : 0u;
+    }
+    if (ln == 63) s_w[w] = x;
+    __syncthreads();
+    unsigned run = x - sum;
+    for (unsigned i = 0; i < w; i++) run += s_w[i];
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        ohist[t * PER + i] = run;
+        run += v[i];
+    }
+}
+
+__global__ __launch_bounds__(ORDER_THREADS) void k_order_scatter(const Header *__restrict__ hdr, unsigned n_max,
+                                                                 const uint2 *__restrict__ groups,
+                                                                 const float *__restrict__ pred,
+                                                                 const uint2 *__restrict__ counts, int mode,
+                                                                 const uint32_t *__restrict__ ohist,
+                                                                 uint32_t *__restrict__ order) {
+    constexpr int NW = ORDER_THREADS / 64;
+    static_assert(NW * ORDER_BUCKETS == 2 * ORDER_THREADS, "two counters per thread to clear");
+    __shared__ unsigned s_base[ORDER_BUCKETS];
+    __shared__ unsigned s_wcnt[NW][ORDER_BUCKETS];
+    if (hdr->flags & ORDER_SKIP) return;
+    const unsigned t = threadIdx.x, w = t >> 6;
+    if (t < ORDER_BUCKETS) s_base[t] = ohist[t * ORDER_BLOCKS + blockIdx.x];
+    unsigned beg, end;
+    order_slice(hdr, n_max, &beg, &end);
+    // No branch below depends on the thread alone (see the walk's queue loop).
+    for (unsigned t0 = beg; t0 < end; t0 += ORDER_THREADS) {
+        (&s_wcnt[0][0])[t] = 0;
+        (&s_wcnt[0][0])[t + ORDER_THREADS] = 0;
+        __syncthreads();
+        const unsigned g = t0 + t;
+        const bool valid = g < end;
+        const unsigned d = valid ? work_bucket(groups, pred, counts, mode, g) : 0u;
+        // lanes of this wave with the same bucket
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 7; bit++) {
+            static_assert(ORDER_BUCKETS <= 128, "7-bit buckets");
+            const unsigned long long m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+        const unsigned rank = rank_below(peers), cnt = (unsigned)__popcll(peers);
+        const bool leader = valid && rank == 0;
+        if (leader) s_wcnt[w][d] = cnt;
+        __syncthreads();
+        if (valid) {
+            unsigned pos = s_base[d] + rank;
+            for (unsigned w2 = 0; w2 < w; w2++) pos += s_wcnt[w2][d];
+            order[pos] = g;
+        }
+        __syncthreads();
+        if (leader) atomicAdd(&s_base[d], cnt);
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_queue_order(const Buffers &b, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_order_hist, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, b.hdr, b.n_max, b.groups, b.pred,
+                       b.gcounts, mode, b.ohist);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(ORDER_SCAN_THREADS), 0, s, b.ohist);
+    hipLaunchKernelGGL(k_order_scatter, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, b.hdr, b.n_max, b.groups,
+                       b.pred, b.gcounts, mode, b.ohist, b.qorder);
     return hipGetLastError();
 }
 

@@ -21,9 +21,9 @@ LIB_PATH = os.path.join(HERE, "libmibh.so")
 PLAIN, KAHAN = 0, 1
 EXPORTS = {
     "keys": 0, "perm": 1, "cells": 2, "groups": 3, "counts": 4, "multipoles": 5, "delta": 6,
-    "mac": 7, "quad": 8, "spos": 9, "features": 10, "predictions": 11,
+    "mac": 7, "quad": 8, "spos": 9, "features": 10, "predictions": 11, "queue": 12,
 }
-BALANCE_EQUAL, BALANCE_ESTIMATOR, BALANCE_EXACT = 0, 1, 2
+ORDER_MORTON, ORDER_ESTIMATOR, ORDER_EXACT = 0, 1, 2
 MLP_FEATURES, MLP_PARAMS = 8, 4801
 STAGES = ("sorting", "moving", "tree_construction", "multipoles", "mac_prep", "walk")
 STATUS = {0: "MIBH_OK", -1: "MIBH_EINVAL", -2: "MIBH_ENOMEM", -3: "MIBH_EHIP", -4: "MIBH_ESTATE",
@@ -84,13 +84,13 @@ def lib():
                   "mibh_export_bytes", "mibh_export"):
             getattr(L, f).restype = st
         L.mibh_group_features.argtypes = [P, C.c_float, P]
-        L.mibh_set_balance.argtypes = [P, C.c_int, P]
+        L.mibh_set_queue_order.argtypes = [P, C.c_int, P]
         L.mibh_mlp_forward.argtypes = [P, P, i64, P, P]
         L.mibh_mlp_scratch_bytes.argtypes = [C.c_int]
         L.mibh_mlp_scratch_bytes.restype = C.c_size_t
         L.mibh_mlp_gradient.argtypes = [P, P, P, P, C.c_int, P, P, P, C.c_size_t, P]
         L.mibh_mlp_adam.argtypes = [P, P, P, P, P, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, P]
-        for f in ("mibh_group_features", "mibh_set_balance", "mibh_mlp_forward", "mibh_mlp_gradient",
+        for f in ("mibh_group_features", "mibh_set_queue_order", "mibh_mlp_forward", "mibh_mlp_gradient",
                   "mibh_mlp_adam"):
             getattr(L, f).restype = st
         L.mibh_profile_begin.argtypes = [P, C.c_int]
@@ -271,9 +271,10 @@ class Context:
         _check(lib().mibh_group_features(self.handle, float(theta), None))
         return self.export("features")
 
-    def set_balance(self, mode: int, w16=None):
-        """Queue split of the walk: BALANCE_EQUAL, BALANCE_ESTIMATOR (float16 weights) or BALANCE_EXACT."""
-        _check(lib().mibh_set_balance(self.handle, int(mode), None if w16 is None else w16.data_ptr()))
+    def set_queue_order(self, mode: int, w16=None):
+        """Order of the walk's group queue: ORDER_MORTON, ORDER_ESTIMATOR (float16 weights, heaviest
+        predicted work first) or ORDER_EXACT (heaviest work of the previous walk of the same tree first)."""
+        _check(lib().mibh_set_queue_order(self.handle, int(mode), None if w16 is None else w16.data_ptr()))
         self._est = w16
 
     def profile_begin(self, max_steps: int):
@@ -303,7 +304,7 @@ class Context:
                 "multipoles": (torch.float64, (-1, 10)), "delta": (torch.float64, (-1,)),
                 "mac": (torch.float32, (-1, 4)), "quad": (torch.float32, (-1, 8)),
                 "spos": (torch.float32, (-1, 4)), "features": (torch.float32, (-1, MLP_FEATURES)),
-                "predictions": (torch.float32, (-1,))}[what]
+                "predictions": (torch.float32, (-1,)), "queue": (torch.int32, (-1,))}[what]
         return buf.view(view[0]).reshape(view[1])
 
 

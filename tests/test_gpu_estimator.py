@@ -93,9 +93,21 @@ def test_training_learns_interaction_counts():
     assert q["rms_log2"] < 0.35 and q["mape"] < 0.3
 
 
-def test_balance_modes_change_nothing_but_the_split():
-    """Equal, estimator (trained or all-zero) and exact splits give bit-identical
-    counts and forces; the estimator split is closer to equal work per queue."""
+def _assert_lpt(q, work):
+    """Heaviest bucket (floor(4 log2 work)) first, Morton order within a bucket:
+    a later group never has more than 2^(1/4) times the work of an earlier one,
+    and the group index drops only where the bucket drops."""
+    w = work[q]
+    prefmin = np.minimum.accumulate(w)
+    assert np.all(w[1:] <= prefmin[:-1] * 2.0 ** 0.25 * (1 + 1e-6))
+    down = q[1:] < q[:-1]
+    assert np.all(w[1:][down] < w[:-1][down])
+
+
+def test_queue_orders_change_nothing_but_the_order():
+    """Morton, estimator (trained or all-zero) and exact-count queue orders give
+    bit-identical counts and forces; the work orders are permutations of the
+    groups, heaviest bucket first, Morton order within a bucket."""
     torch = _torch()
     from paper_1204_2280_amd import estimator, mibh
     pos, mass = W.two_plummers(1 << 16)
@@ -105,16 +117,20 @@ def test_balance_modes_change_nothing_but_the_split():
     x, t = _walk_data(ctx, pos, mass, 0.75)
     w32, w16, _ = estimator.train(x, t, steps=400, batch=1024, lr=3e-3)
     zero16 = torch.zeros(mibh.MLP_PARAMS, dtype=torch.float16, device=ctx.device)
-    ref = None
-    works = {}
     counts = ctx.export("counts").view(torch.int32).reshape(-1, 2).cpu().numpy().astype(np.int64)
     gn = mibh.Decoded.groups(ctx.export("groups"))["count"]
-    work = gn * (1 + counts[:, 0] + counts[:, 1])
-    for mode, w in ((mibh.BALANCE_EQUAL, None), (mibh.BALANCE_ESTIMATOR, w16), (mibh.BALANCE_ESTIMATOR, zero16),
-                    (mibh.BALANCE_EXACT, None)):
-        ctx.set_balance(mode, w)
+    work = (gn * (1 + counts[:, 0] + counts[:, 1])).astype(np.float64)
+    ng = len(gn)
+    ref = None
+    queues = {}
+    for name, mode, w in (("morton", mibh.ORDER_MORTON, None), ("estimator", mibh.ORDER_ESTIMATOR, w16),
+                          ("zero", mibh.ORDER_ESTIMATOR, zero16), ("exact", mibh.ORDER_EXACT, None)):
+        ctx.set_queue_order(mode, w)
         acc, pot = ctx.forces(p, m, 0.75)
-        if mode == mibh.BALANCE_EXACT:
+        if mode == mibh.ORDER_EXACT:
+            ctx.sync()
+            with pytest.raises(mibh.MibhError):  # a new tree has no counts yet: Morton order
+                ctx.export("queue")
             acc, pot = ctx.compute_forces(0.75)  # a second walk of the same tree has exact counts
         ctx.sync()
         c = ctx.export("counts").view(torch.int32).cpu().numpy()
@@ -123,13 +139,16 @@ def test_balance_modes_change_nothing_but_the_split():
             ref = got
         for a, b in zip(ref, got):
             np.testing.assert_array_equal(a, b)
-        if mode == mibh.BALANCE_ESTIMATOR and w is w16:
-            pred = ctx.export("predictions").cpu().numpy().astype(np.float64)
-            pw = gn * np.exp2(np.clip(pred, 0, 40))
-            cut = np.searchsorted(np.cumsum(pw), np.sum(pw) * np.arange(1, 8) / 8.0)
-            works["estimator"] = [int(s.sum()) for s in np.split(work, cut)]
-    eq = [int(s.sum()) for s in np.array_split(work, 8)]
-    imb_eq = max(eq) / np.mean(eq)
-    imb_est = max(works["estimator"]) / np.mean(works["estimator"])
-    print(f"[gpu] queue work max/mean: equal split {imb_eq:.3f}, estimator split {imb_est:.3f}", flush=True)
-    assert imb_est <= imb_eq
+        if mode != mibh.ORDER_MORTON:
+            q = ctx.export("queue").cpu().numpy().astype(np.int64)
+            np.testing.assert_array_equal(np.sort(q), np.arange(ng))
+            queues[name] = q
+    # all-zero weights predict y = 0: the work is the group size
+    _assert_lpt(queues["zero"], gn.astype(np.float64))
+    _assert_lpt(queues["exact"], work)
+    # the estimator order puts heavy groups first
+    k = ng // 10
+    ws = work[queues["estimator"]]
+    ratio = ws[:k].mean() / ws[-k:].mean()
+    print(f"[gpu] estimator queue: mean work first tenth / last tenth = {ratio:.2f}", flush=True)
+    assert ratio > 2.0

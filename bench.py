@@ -178,6 +178,60 @@ def bench_variant_ensemble(theta, steps, warmup, nsys=64, seed=4):
                 (st["sum_pc"] + st["sum_pp"]) / (ms_batch * 1e-3)}
 
 
+def bench_variant_queue_order(pos, mass, theta, steps, warmup):
+    """Walk time of the same workload for the three queue orders: Morton;
+    longest-processing-time first by the exact counts of the previous walk of
+    the same tree; and by the learned estimator (trained here on three smaller
+    Plummer spheres of other seeds).  The step time with the estimator includes
+    its feature and forward kernels (in the mac_prep stage)."""
+    import torch
+    from paper_1204_2280_amd import estimator, mibh, workloads
+    n = len(mass)
+    dev = torch.device("cuda", 0)
+    p = torch.from_numpy(pos).to(dev)
+    m = torch.from_numpy(mass).to(dev)
+    # estimator training data: walks of smaller systems
+    xs, ts = [], []
+    for k, nt in enumerate((1 << 16, 1 << 17, 1 << 18)):
+        pt, _, mt = workloads.plummer(nt, 100 + k, with_velocities=False)
+        c = mibh.Context(nt, device=dev)
+        c.forces(torch.from_numpy(pt).to(dev), torch.from_numpy(mt).to(dev), theta)
+        c.sync()
+        x, t = estimator.collect(c, theta)
+        xs.append(x)
+        ts.append(t)
+        del c
+    _, w16, _ = estimator.train(torch.cat(xs), torch.cat(ts), steps=800, batch=1024, lr=3e-3)
+    ctx = mibh.Context(n, device=dev)
+
+    def stages(run):
+        for _ in range(warmup):
+            run()
+        ctx.sync()
+        ctx.profile_begin(steps)
+        for _ in range(steps):
+            run()
+        rec = ctx.profile_read()
+        return {k: sum(r[k] for r in rec) / len(rec) for k in rec[0]}
+
+    out = {}
+    ctx.set_queue_order(mibh.ORDER_MORTON)
+    st = stages(lambda: ctx.forces(p, m, theta))
+    out["morton"] = {"walk_ms": st["walk"], "step_ms": sum(st.values())}
+    ctx.set_queue_order(mibh.ORDER_ESTIMATOR, w16)
+    st = stages(lambda: ctx.forces(p, m, theta))
+    out["estimator"] = {"walk_ms": st["walk"], "mac_prep_ms": st["mac_prep"], "step_ms": sum(st.values())}
+    x, t = estimator.collect(ctx, theta)
+    out["estimator"]["quality"] = estimator.evaluate(w16, x, t)
+    ctx.set_queue_order(mibh.ORDER_EXACT)
+    ctx.compute_forces(theta)  # exact counts of this tree
+    st = stages(lambda: ctx.compute_forces(theta))
+    out["exact_counts"] = {"walk_ms": st["walk"], "mac_prep_ms": st["mac_prep"],
+                           "note": "repeated walks of one tree (the counts of a new tree are not known)"}
+    del ctx
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +354,8 @@ def main():
         result["variant_kahan"] = bench_variant_kahan(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variant: batched ensemble")
         result["variant_ensemble"] = bench_variant_ensemble(theta, max(3, args.steps // 4), 1)
+        log("[bench] variant: queue order")
+        result["variant_queue_order"] = bench_variant_queue_order(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variants done")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

@@ -194,7 +194,8 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes);
  * keys, radix sort), moving (reorder), tree construction (octree, groups),
  * multipole moments, MAC preparation and the tree traverse (walk kernel).
  * mibh_profile_begin(ctx, max_steps) starts recording one set of events per
- * step (a step ends at compute_forces) for up to max_steps steps;
+ * step (a step ends at compute_forces) for up to max_steps steps; stages a
+ * step skips (a compute_forces on an existing tree) are empty;
  * mibh_profile_read synchronises, writes ms[step][MIBH_NSTAGES] for the
  * recorded steps, sets *nsteps and stops recording.  Errors: EINVAL, EHIP. */
 enum {

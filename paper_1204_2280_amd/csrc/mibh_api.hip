@@ -39,6 +39,7 @@ struct mibh_ctx {
     // stage events: MIBH_NSTAGES + 1 per profiled step
     hipEvent_t *events;
     int prof_max, prof_step;
+    int prof_last;            // last stage recorded in the current step (-2: none)
 };
 
 namespace {
@@ -216,6 +217,7 @@ mibh_status mibh_create(const mibh_params *pp, int64_t n_max, void *d_workspace,
     c->acc = c->pot = nullptr;
     c->events = nullptr;
     c->prof_max = c->prof_step = 0;
+    c->prof_last = -2;
     c->nsys = 1;
     c->order = c->last_order = MIBH_ORDER_MORTON;
     c->est_w16 = nullptr;
@@ -250,8 +252,12 @@ static void free_events(mibh_ctx *ctx) {
 // Records the event that ends stage `stage` (stage -1: the step's start).
 static mibh_status mark(mibh_ctx *ctx, int stage) {
     if (!ctx->events || ctx->prof_step >= ctx->prof_max) return MIBH_OK;
-    hipEvent_t e = ctx->events[ctx->prof_step * (MIBH_NSTAGES + 1) + stage + 1];
-    HIP_TRY(hipEventRecord(e, ctx->stream), "hipEventRecord");
+    // stages that this step skipped (a walk of an existing tree) end here: zero length
+    for (int s = ctx->prof_last + 1; s <= stage; s++) {
+        hipEvent_t e = ctx->events[ctx->prof_step * (MIBH_NSTAGES + 1) + s + 1];
+        HIP_TRY(hipEventRecord(e, ctx->stream), "hipEventRecord");
+    }
+    if (stage > ctx->prof_last) ctx->prof_last = stage;
     return MIBH_OK;
 }
 
@@ -314,6 +320,7 @@ mibh_status mibh_compute_multipoles(mibh_ctx *ctx) {
     mibh_status st = check_ctx(ctx);
     if (st) return st;
     if (ctx->state < 1) return fail(MIBH_ESTATE, "compute_multipoles before build_tree");
+    if ((st = mark(ctx, MIBH_STAGE_BUILD))) return st;  // no-op after a build in this step
     HIP_TRY(launch_multipoles(ctx->b, (unsigned)ctx->nsys, ctx->stream), "multipoles");
     if ((st = mark(ctx, MIBH_STAGE_MULTIPOLES))) return st;
     ctx->state = 2;
@@ -327,6 +334,7 @@ mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float 
     if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
     if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
     const double inv_theta = 1.0 / (double)theta;
+    if ((st = mark(ctx, MIBH_STAGE_MULTIPOLES))) return st;  // no-op after compute_multipoles in this step
     HIP_TRY(launch_mac_prep(ctx->b, (unsigned)ctx->nsys, inv_theta, ctx->stream), "mac_prep");
     int mode = ctx->order;
     if (mode == MIBH_ORDER_EXACT && !ctx->counts_valid) mode = MIBH_ORDER_MORTON;  // no walk of this tree yet
@@ -342,7 +350,10 @@ mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float 
     ctx->last_order = mode;
     if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;
     ctx->counts_valid = 1;
-    if (ctx->events && ctx->prof_step < ctx->prof_max) ctx->prof_step++;
+    if (ctx->events && ctx->prof_step < ctx->prof_max) {
+        ctx->prof_step++;
+        ctx->prof_last = -2;
+    }
     ctx->acc = d_acc;
     ctx->pot = d_pot;
     ctx->state = 3;
@@ -619,6 +630,7 @@ mibh_status mibh_profile_begin(mibh_ctx *ctx, int max_steps) {
     if (!ctx->events) return fail(MIBH_ENOMEM, "host allocation failed");
     ctx->prof_max = max_steps;
     ctx->prof_step = 0;
+    ctx->prof_last = -2;
     for (int i = 0; i < ne; i++) {
         hipError_t e = hipEventCreate(&ctx->events[i]);
         if (e != hipSuccess) {

@@ -222,3 +222,25 @@ def test_error_paths(ctx):
     c.sync()
     with pytest.raises(mibh.MibhError):
         gpu_context(10, ncrit=65, group_cap=64)
+
+
+def test_stage_profile():
+    """Stage events: a full step times every stage; a walk of the same tree
+    times mac_prep and the walk only, the build stages are empty (two events
+    recorded back to back)."""
+    import torch
+    pos, _, mass = W.plummer(1 << 15, 21, with_velocities=False)
+    ctx = gpu_context(len(mass))
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    ctx.profile_begin(3)
+    ctx.forces(p, m, 0.75)
+    ctx.compute_forces(0.75)
+    ctx.forces(p, m, 0.75)
+    rec = ctx.profile_read()
+    print(f"[gpu] stage profile {rec}", flush=True)
+    assert len(rec) == 3
+    for r in (rec[0], rec[2]):
+        assert all(v > 0 for v in r.values())
+    assert all(rec[1][k] < 0.05 for k in ("sorting", "moving", "tree_construction", "multipoles"))
+    assert rec[1]["mac_prep"] > 0 and rec[1]["walk"] > 0

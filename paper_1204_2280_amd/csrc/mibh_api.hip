@@ -118,6 +118,7 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.vals[1] = (uint32_t *)take(4 * n);
     t.hist = (uint32_t *)take(4 * RADIX * ntiles);
     t.btot = (uint32_t *)take(4 * RADIX);
+    t.ppack = (float4 *)take(16 * n);
     t.spos = (float4 *)take(16 * n);
     t.cl = (int8_t *)take(n);
     t.lvinfo = (uchar4 *)take(4 * n);
@@ -293,10 +294,10 @@ mibh_status mibh_build_tree_batch(mibh_ctx *ctx, const float *d_pos, const float
     hipLaunchKernelGGL(k_set_offsets, dim3(1), dim3(256), 0, s, o, ctx->b.sys_off);
     HIP_TRY(hipGetLastError(), "set_offsets");
     HIP_TRY(launch_bbox(ctx->b, d_pos, d_mass, un, us, s), "bbox");
-    HIP_TRY(launch_keys(ctx->b, d_pos, un, us, s), "keys");
+    HIP_TRY(launch_keys(ctx->b, d_pos, d_mass, un, us, s), "keys");
     HIP_TRY(launch_sort(ctx->b, un, us, s), "sort");
     if ((st = mark(ctx, MIBH_STAGE_SORT))) return st;
-    HIP_TRY(launch_reorder(ctx->b, d_pos, d_mass, un, us, s), "reorder");
+    HIP_TRY(launch_reorder(ctx->b, un, us, s), "reorder");
     if ((st = mark(ctx, MIBH_STAGE_MOVE))) return st;
     HIP_TRY(launch_build(ctx->b, un, us, ctx->p.ncrit, ctx->p.group_cap, s), "build");
     if ((st = mark(ctx, MIBH_STAGE_BUILD))) return st;

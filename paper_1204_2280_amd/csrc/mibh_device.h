@@ -81,6 +81,7 @@ struct Buffers {
     uint32_t *vals[2];
     uint32_t *hist;         // [RADIX][ntiles]
     uint32_t *btot;         // [RADIX]
+    float4 *ppack;          // input x, y, z, m packed by the keys kernel (one line per gather)
     float4 *spos;           // sorted x, y, z, m
     int8_t *cl;             // common leading octal digits with the previous key (-1 at 0)
     uchar4 *lvinfo;         // per particle: first level started, leaf level, group level, group start
@@ -116,12 +117,12 @@ __device__ __forceinline__ unsigned system_of(const uint32_t *__restrict__ sys_o
 // Host launchers (kernels live in the .hip files).
 hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
                        hipStream_t s);
-hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, unsigned nsys, hipStream_t s);
+hipError_t launch_keys(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
+                       hipStream_t s);
 hipError_t launch_sort(const Buffers &b, unsigned n, unsigned nsys, hipStream_t s);
 // buffer (0 or 1) that holds the sorted keys and permutation after launch_sort
 inline int sorted_buffer(unsigned nsys) { return nsys > 1 ? (SORT_PASSES + 1) & 1 : SORT_PASSES & 1; }
-hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
-                          hipStream_t s);
+hipError_t launch_reorder(const Buffers &b, unsigned n, unsigned nsys, hipStream_t s);
 hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, int gcap, hipStream_t s);
 hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s);
 hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double inv_theta, hipStream_t s);

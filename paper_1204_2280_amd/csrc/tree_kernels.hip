@@ -256,19 +256,23 @@ hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, un
 // q_x, q_y, q_z at 3b+2, 3b+1, 3b.
 // --------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ pos, unsigned n, unsigned nsys,
-                                              const uint32_t *__restrict__ sys_off,
+// Also packs (x, y, z, m) of every particle into one float4, so that the
+// reorder gathers one 16-byte record per particle instead of two.
+__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ pos, const float *__restrict__ mass,
+                                              unsigned n, unsigned nsys, const uint32_t *__restrict__ sys_off,
                                               const SysCube *__restrict__ cube, uint64_t *__restrict__ keys,
-                                              uint8_t *__restrict__ sys8) {
+                                              uint8_t *__restrict__ sys8, float4 *__restrict__ ppack) {
     const unsigned i = blockIdx.x * 256u + threadIdx.x;
     if (i >= n) return;
     const unsigned sys = nsys > 1 ? system_of(sys_off, nsys, i) : 0u;
     const SysCube c = cube[sys];
     const double s = ldexp(1.0, KEY_LEVELS - c.k);
+    const float x[3] = {pos[(size_t)i * 3], pos[(size_t)i * 3 + 1], pos[(size_t)i * 3 + 2]};
+    ppack[i] = make_float4(x[0], x[1], x[2], mass[i]);
     uint64_t q[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        double f = floor(((double)pos[(size_t)i * 3 + a] - (double)c.lo[a]) * s);
+        double f = floor(((double)x[a] - (double)c.lo[a]) * s);
         if (!(f >= 0.0)) f = 0.0;
         if (f > 1048575.0) f = 1048575.0;
         q[a] = (uint64_t)f;
@@ -277,9 +281,10 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ pos, uns
     if (nsys > 1) sys8[i] = (uint8_t)sys;
 }
 
-hipError_t launch_keys(const Buffers &b, const float *pos, unsigned n, unsigned nsys, hipStream_t s) {
-    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, s, pos, n, nsys, b.sys_off, b.cube,
-                       b.keys[0], b.sys8);
+hipError_t launch_keys(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, s, pos, mass, n, nsys, b.sys_off, b.cube,
+                       b.keys[0], b.sys8, b.ppack);
     return hipGetLastError();
 }
 
@@ -345,23 +350,27 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist,
     if (threadIdx.x == 0) btot[blockIdx.x] = total;
 }
 
+// Ranks every element of the tile (digit, then input order), stages the tile
+// in LDS in that order and writes it out from there: consecutive threads then
+// write consecutive addresses of each digit's run.
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint8_t *__restrict__ sys8, unsigned n, int shift,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ btot, unsigned ntiles) {
     constexpr int NW = SORT_THREADS / 64;
+    static_assert(SORT_THREADS == RADIX, "one thread per digit");
     __shared__ uint32_t wcnt[NW][RADIX];
-    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint32_t gshift[RADIX];  // output position of tile position i of digit d: gshift[d] + i
     __shared__ unsigned s_wave[NW + 1];
+    __shared__ uint64_t s_key[SORT_TILE];
+    __shared__ uint32_t s_val[SORT_TILE];
     const unsigned w = threadIdx.x >> 6, ln = lane64();
-    // digit bases: exclusive scan of the digit totals + this tile's offset in the digit row
-    {
-        const unsigned d = threadIdx.x;  // SORT_THREADS == RADIX
-        unsigned total;
-        const unsigned ex = block_excl_scan<SORT_THREADS>(btot[d], s_wave, &total);
-        gbase[d] = ex + hist[(size_t)d * ntiles + blockIdx.x];
-        for (int v = 0; v < NW; v++) wcnt[v][d] = 0;
-    }
+    const unsigned dt = threadIdx.x;  // the digit this thread looks after
+    unsigned total;
+    // start of digit dt's run of this tile in the output
+    const unsigned gstart = block_excl_scan<SORT_THREADS>(btot[dt], s_wave, &total) +
+                            hist[(size_t)dt * ntiles + blockIdx.x];
+    for (int v = 0; v < NW; v++) wcnt[v][dt] = 0;
     __syncthreads();
     const unsigned base = blockIdx.x * SORT_TILE + w * (64 * SORT_ITEMS);
     uint64_t key[SORT_ITEMS];
@@ -380,13 +389,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
     {
-        const unsigned d = threadIdx.x;
+        // tile position of the first element of digit dt from wave v: digits
+        // before dt, then waves before v
         unsigned run = 0;
         for (int v = 0; v < NW; v++) {
-            const unsigned c = wcnt[v][d];
-            wcnt[v][d] = run;
+            const unsigned c = wcnt[v][dt];
+            wcnt[v][dt] = run;
             run += c;
         }
+        const unsigned lstart = block_excl_scan<SORT_THREADS>(run, s_wave, &total);
+        for (int v = 0; v < NW; v++) wcnt[v][dt] += lstart;
+        gshift[dt] = gstart - lstart;  // modulo 2^32; gshift + i >= 0 for the tile positions of dt
     }
     __syncthreads();
 #pragma unroll
@@ -394,10 +407,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         const unsigned idx = base + t * 64 + ln;
         if (idx < n) {
             const unsigned d = radix_digit(key[t], val[t], shift, sys8);
-            const unsigned p = gbase[d] + wcnt[w][d] + rank[t];
-            kout[p] = key[t];
-            vout[p] = val[t];
+            const unsigned lp = wcnt[w][d] + rank[t];
+            s_key[lp] = key[t];
+            s_val[lp] = val[t];
         }
+    }
+    __syncthreads();
+    const unsigned cnt = min((unsigned)SORT_TILE, n - blockIdx.x * SORT_TILE);
+    for (unsigned i = threadIdx.x; i < cnt; i += SORT_THREADS) {
+        const uint64_t k = s_key[i];
+        const uint32_t v = s_val[i];
+        const unsigned p = gshift[radix_digit(k, v, shift, sys8)] + i;
+        kout[p] = k;
+        vout[p] = v;
     }
 }
 
@@ -423,25 +445,22 @@ hipError_t launch_sort(const Buffers &b, unsigned n, unsigned nsys, hipStream_t 
 // Moving: gather (x, y, z, m) into key order; shared digits with the previous key.
 // --------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_reorder(const float *__restrict__ pos,
-                                                 const float *__restrict__ mass,
+__global__ __launch_bounds__(256) void k_reorder(const float4 *__restrict__ ppack,
                                                  const uint64_t *__restrict__ keys,
                                                  const uint32_t *__restrict__ perm, unsigned n, unsigned nsys,
                                                  const uint32_t *__restrict__ sys_off,
                                                  float4 *__restrict__ spos, int8_t *__restrict__ cl) {
     const unsigned k = blockIdx.x * 256u + threadIdx.x;
     if (k >= n) return;
-    const size_t j = perm[k];
-    spos[k] = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], mass[j]);
+    spos[k] = ppack[perm[k]];
     // a system's first particle opens cells at every level, like particle 0
     const bool start = k == 0 || (nsys > 1 && sys_off[system_of(sys_off, nsys, k)] == k);
     cl[k] = start ? (int8_t)-1 : (int8_t)shared_digits(keys[k - 1], keys[k]);
 }
 
-hipError_t launch_reorder(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
-                          hipStream_t s) {
+hipError_t launch_reorder(const Buffers &b, unsigned n, unsigned nsys, hipStream_t s) {
     const int sb = sorted_buffer(nsys);
-    hipLaunchKernelGGL(k_reorder, dim3((n + 255) / 256), dim3(256), 0, s, pos, mass, b.keys[sb], b.vals[sb],
+    hipLaunchKernelGGL(k_reorder, dim3((n + 255) / 256), dim3(256), 0, s, b.ppack, b.keys[sb], b.vals[sb],
                        n, nsys, b.sys_off, b.spos, b.cl);
     return hipGetLastError();
 }
@@ -683,6 +702,8 @@ hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, 
 // fma calls, so every run gives the same bits.
 // --------------------------------------------------------------------------
 
+constexpr unsigned LEAF_REGS = 16;  // leaves up to this size are summed from registers
+
 __global__ __launch_bounds__(256) void k_multipole_level(
     int lev, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
     const float4 *__restrict__ spos, const uint64_t *__restrict__ keys, double *__restrict__ mp,
@@ -707,7 +728,39 @@ __global__ __launch_bounds__(256) void k_multipole_level(
         }
         double M = 0.0, cm[3] = {0.0, 0.0, 0.0}, com[3];
         double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (nch == 0) {
+        if (nch == 0 && t.y <= LEAF_REGS) {
+            // a leaf of up to LEAF_REGS particles: all loads in flight at once,
+            // both passes from registers (same operations in the same order)
+            float4 pr[LEAF_REGS];
+#pragma unroll
+            for (int j = 0; j < LEAF_REGS; j++)
+                pr[j] = (unsigned)j < t.y ? spos[t.x + j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int j = 0; j < LEAF_REGS; j++) {
+                if ((unsigned)j < t.y) {
+                    const double m = (double)pr[j].w;
+                    M = M + m;
+                    cm[0] = fma(m, (double)pr[j].x, cm[0]);
+                    cm[1] = fma(m, (double)pr[j].y, cm[1]);
+                    cm[2] = fma(m, (double)pr[j].z, cm[2]);
+                }
+            }
+            for (int a = 0; a < 3; a++) com[a] = M > 0.0 ? cm[a] / M : centre[a];
+#pragma unroll
+            for (int j = 0; j < LEAF_REGS; j++) {
+                if ((unsigned)j < t.y) {
+                    const double m = (double)pr[j].w;
+                    const double dx = (double)pr[j].x - com[0], dy = (double)pr[j].y - com[1],
+                                 dz = (double)pr[j].z - com[2];
+                    S[0] = fma(m * dx, dx, S[0]);
+                    S[1] = fma(m * dy, dy, S[1]);
+                    S[2] = fma(m * dz, dz, S[2]);
+                    S[3] = fma(m * dx, dy, S[3]);
+                    S[4] = fma(m * dx, dz, S[4]);
+                    S[5] = fma(m * dy, dz, S[5]);
+                }
+            }
+        } else if (nch == 0) {
             for (unsigned j = t.x; j < t.x + t.y; j++) {
                 const float4 p = spos[j];
                 const double m = (double)p.w;

@@ -178,22 +178,21 @@ def bench_variant_ensemble(theta, steps, warmup, nsys=64, seed=4):
                 (st["sum_pc"] + st["sum_pp"]) / (ms_batch * 1e-3)}
 
 
-def bench_variant_queue_order(pos, mass, theta, steps, warmup):
-    """Walk time of the same workload for the three queue orders: Morton;
-    longest-processing-time first by the exact counts of the previous walk of
-    the same tree; and by the learned estimator (trained here on three smaller
-    Plummer spheres of other seeds).  The step time with the estimator includes
-    its feature and forward kernels (in the mac_prep stage)."""
+def bench_variant_queue_order(pos_train, mass_train, theta, steps, warmup):
+    """Walk time for the three queue orders on two Plummer spheres of 2^21
+    particles each (seeds 5 and 6, 10 apart): Morton; longest-processing-time
+    first by the exact counts of the previous walk of the same tree; and by the
+    learned estimator, trained on the per-group counts of Plummer spheres of
+    2^15 (seed 1), 2^20 (seed 2) and the headline 2^22 system (given).  The
+    step time with the estimator includes its feature and forward kernels (in
+    the mac_prep stage)."""
     import torch
     from paper_1204_2280_amd import estimator, mibh, workloads
-    n = len(mass)
     dev = torch.device("cuda", 0)
-    p = torch.from_numpy(pos).to(dev)
-    m = torch.from_numpy(mass).to(dev)
-    # estimator training data: walks of smaller systems
     xs, ts = [], []
-    for k, nt in enumerate((1 << 16, 1 << 17, 1 << 18)):
-        pt, _, mt = workloads.plummer(nt, 100 + k, with_velocities=False)
+    for pt, mt in [workloads.plummer(1 << 15, 1, with_velocities=False)[::2],
+                   workloads.plummer(1 << 20, 2, with_velocities=False)[::2], (pos_train, mass_train)]:
+        nt = len(mt)
         c = mibh.Context(nt, device=dev)
         c.forces(torch.from_numpy(pt).to(dev), torch.from_numpy(mt).to(dev), theta)
         c.sync()
@@ -201,7 +200,11 @@ def bench_variant_queue_order(pos, mass, theta, steps, warmup):
         xs.append(x)
         ts.append(t)
         del c
-    _, w16, _ = estimator.train(torch.cat(xs), torch.cat(ts), steps=800, batch=1024, lr=3e-3)
+    _, w16, _ = estimator.train(torch.cat(xs), torch.cat(ts), steps=1000, batch=1024, lr=3e-3)
+    pos, mass = workloads.two_plummers(1 << 21)
+    n = len(mass)
+    p = torch.from_numpy(pos).to(dev)
+    m = torch.from_numpy(mass).to(dev)
     ctx = mibh.Context(n, device=dev)
 
     def stages(run):
@@ -229,7 +232,44 @@ def bench_variant_queue_order(pos, mass, theta, steps, warmup):
     out["exact_counts"] = {"walk_ms": st["walk"], "mac_prep_ms": st["mac_prep"],
                            "note": "repeated walks of one tree (the counts of a new tree are not known)"}
     del ctx
+    out["workload"] = f"two_plummers_2x2^21_seeds5_6_sep10_theta{theta:g}"
     return out
+
+
+def bench_variant_leapfrog(n, seed, theta, steps):
+    """Shared-time-step kick-drift-kick driver on the same Plummer sphere with
+    its velocities: milliseconds per step (one force step and two fused
+    kick/drift launches; the initial force evaluation is timed too and spread
+    over the steps) and the float64 energy drift over the run (dt = 1/128,
+    softening eps = 0.01: with no softening the closest pairs of 2^22 bodies
+    need far smaller steps than a shared dt gives them)."""
+    import torch
+    from paper_1204_2280_amd import mibh, workloads
+    pos, vel, mass = workloads.plummer(n, seed)
+    dev = torch.device("cuda", 0)
+    P, V, M = (torch.from_numpy(t.copy()).to(dev) for t in (pos, vel, mass))
+    eps2 = 1e-4
+    ctx = mibh.Context(n, device=dev, eps2=eps2)
+    dt = 1.0 / 128
+    ctx.leapfrog(P, V, M, theta, dt, 1)  # warm-up
+    P.copy_(torch.from_numpy(pos))
+    V.copy_(torch.from_numpy(vel))
+    ctx.sync()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(ctx.stream)
+    ctx.leapfrog(P, V, M, theta, dt, steps)
+    b.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    P.copy_(torch.from_numpy(pos))
+    V.copy_(torch.from_numpy(vel))
+    _, _, log = ctx.leapfrog(P, V, M, theta, dt, steps, log_every=max(1, steps // 4))
+    E = log[:, 1] + log[:, 2]
+    del ctx
+    return {"workload": f"plummer_n{n}_seed{seed}_theta{theta:g}_dt{dt:g}_eps2{eps2:g}", "steps": steps,
+            "ms_per_step": ms, "particles_per_s": n / (ms * 1e-3),
+            "energy_log": [[float(t), float(T), float(W)] for t, T, W in log],
+            "rel_energy_drift": float(abs(E[-1] - E[0]) / abs(E[0]))}
 
 
 def main():
@@ -354,6 +394,8 @@ def main():
         result["variant_kahan"] = bench_variant_kahan(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variant: batched ensemble")
         result["variant_ensemble"] = bench_variant_ensemble(theta, max(3, args.steps // 4), 1)
+        log("[bench] variant: leapfrog driver")
+        result["variant_leapfrog"] = bench_variant_leapfrog(n, args.seed, theta, 20)
         log("[bench] variant: queue order")
         result["variant_queue_order"] = bench_variant_queue_order(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variants done")

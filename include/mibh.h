@@ -162,6 +162,31 @@ mibh_status mibh_stats(mibh_ctx *ctx, mibh_stats_t *out);
  * d_vel [n][3] (NULL: T = 0).  Synchronises.  Errors: ESTATE. */
 mibh_status mibh_energy(mibh_ctx *ctx, const float *d_vel, double *T, double *W);
 
+/* Shared-time-step integration.  The paper integrates every step on the GPU
+ * with no host traffic (Introduction, Results section) but does not name its
+ * integrator; this library uses the kick-drift-kick leapfrog (second order,
+ * time-reversible) on float32 state, each update one fused multiply-add.
+ *
+ * mibh_kick_drift: v <- v + dt_kick a, then, if dt_drift != 0,
+ * x <- x + dt_drift v with the updated v, for n particles (device arrays
+ * [n][3], updated in place; a as written by compute_forces, G included).
+ * Enqueues one kernel.  Errors: EINVAL (null pointer, n out of range,
+ * non-finite step).
+ *
+ * mibh_leapfrog: nsteps steps of size dt (negative dt integrates backwards):
+ * forces at the initial positions, then per step kick(dt/2) + drift(dt),
+ * forces (a full rebuild: shared time steps), kick(dt/2).  d_acc and d_pot
+ * [n][3], [n] receive the forces of the final positions.  With
+ * log_every > 0, h_log (host, log_cap >= nsteps/log_every + 1 rows) gets
+ * rows (t, T, W) in float64 (mibh_energy) at step 0 and every log_every
+ * steps, *nlog the number of rows; each row synchronises.  Errors: as
+ * mibh_forces and mibh_energy, EINVAL for a short log. */
+mibh_status mibh_kick_drift(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_acc, int64_t n,
+                            float dt_kick, float dt_drift);
+mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_mass, int64_t n,
+                          float theta, float dt, int nsteps, int log_every, float *d_acc, float *d_pot,
+                          double *h_log, int log_cap, int *nlog);
+
 /* Device-to-device copy of an internal array of the current tree (for tests
  * and tools).  bytes must be at least the size reported by mibh_export_bytes.
  *   MIBH_EXPORT_KEYS    uint64 [n]        sorted Morton keys

@@ -371,6 +371,54 @@ mibh_status mibh_forces(mibh_ctx *ctx, const float *d_pos, const float *d_mass, 
     return mibh_compute_forces(ctx, theta, d_acc, d_pot);
 }
 
+mibh_status mibh_kick_drift(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_acc, int64_t n,
+                            float dt_kick, float dt_drift) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!d_pos || !d_vel || !d_acc) return fail(MIBH_EINVAL, "null pointer");
+    if (n < 1 || n > ctx->n_max)
+        return fail(MIBH_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)ctx->n_max);
+    if (!isfinite(dt_kick) || !isfinite(dt_drift)) return fail(MIBH_EINVAL, "time steps must be finite");
+    HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, (unsigned)n, dt_kick, dt_drift, ctx->stream), "kick_drift");
+    return MIBH_OK;
+}
+
+mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_mass, int64_t n, float theta,
+                          float dt, int nsteps, int log_every, float *d_acc, float *d_pot, double *h_log,
+                          int log_cap, int *nlog) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!d_pos || !d_vel || !d_mass || !d_acc || !d_pot) return fail(MIBH_EINVAL, "null pointer");
+    if (!isfinite(dt)) return fail(MIBH_EINVAL, "dt must be finite");
+    if (nsteps < 0 || log_every < 0) return fail(MIBH_EINVAL, "nsteps and log_every must be >= 0");
+    const int need = log_every > 0 ? nsteps / log_every + 1 : 0;
+    if (need > 0 && (!h_log || log_cap < need))
+        return fail(MIBH_EINVAL, "energy log needs %d entries, capacity %d", need, log_cap);
+    int k = 0;
+    if (nlog) *nlog = 0;
+    auto record = [&](int step) -> mibh_status {
+        double T = 0.0, W = 0.0;
+        mibh_status s2 = mibh_energy(ctx, d_vel, &T, &W);
+        if (s2) return s2;
+        h_log[3 * k] = (double)step * (double)dt;
+        h_log[3 * k + 1] = T;
+        h_log[3 * k + 2] = W;
+        k++;
+        if (nlog) *nlog = k;
+        return MIBH_OK;
+    };
+    const float half = 0.5f * dt;
+    if ((st = mibh_forces(ctx, d_pos, d_mass, n, theta, d_acc, d_pot))) return st;
+    if (log_every > 0 && (st = record(0))) return st;
+    for (int s = 1; s <= nsteps; s++) {
+        HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, (unsigned)n, half, dt, ctx->stream), "kick_drift");
+        if ((st = mibh_forces(ctx, d_pos, d_mass, n, theta, d_acc, d_pot))) return st;
+        HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, (unsigned)n, half, 0.0f, ctx->stream), "kick");
+        if (log_every > 0 && s % log_every == 0 && (st = record(s))) return st;
+    }
+    return MIBH_OK;
+}
+
 mibh_status mibh_sync(mibh_ctx *ctx) {
     mibh_status st = check_ctx(ctx);
     if (st) return st;

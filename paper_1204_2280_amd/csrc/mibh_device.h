@@ -140,6 +140,9 @@ hipError_t launch_adam(float *w32, void *w16, const float *grad, float *m, float
 // Writes b.qorder: the groups ordered by work, heaviest first; mode 1: work
 // predicted by the estimator (b.pred), 2: exact counts of the last walk.
 hipError_t launch_queue_order(const Buffers &b, int mode, hipStream_t s);
+// v <- v + dt_kick a, then (dt_drift != 0) x <- x + dt_drift v, for n particles
+hipError_t launch_kick_drift(float *pos, float *vel, const float *acc, unsigned n, float dt_kick, float dt_drift,
+                             hipStream_t s);
 hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
                          unsigned n, double *d_out2, hipStream_t s);
 

@@ -83,6 +83,11 @@ def lib():
                   "mibh_compute_forces", "mibh_forces", "mibh_sync", "mibh_stats", "mibh_energy",
                   "mibh_export_bytes", "mibh_export"):
             getattr(L, f).restype = st
+        L.mibh_kick_drift.argtypes = [P, P, P, P, i64, C.c_float, C.c_float]
+        L.mibh_leapfrog.argtypes = [P, P, P, P, i64, C.c_float, C.c_float, C.c_int, C.c_int, P, P, P, C.c_int,
+                                    C.POINTER(C.c_int)]
+        L.mibh_kick_drift.restype = st
+        L.mibh_leapfrog.restype = st
         L.mibh_group_features.argtypes = [P, C.c_float, P]
         L.mibh_set_queue_order.argtypes = [P, C.c_int, P]
         L.mibh_mlp_forward.argtypes = [P, P, i64, P, P]
@@ -252,6 +257,46 @@ class Context:
         self.build_tree(pos, mass)
         self.compute_multipoles()
         return self.compute_forces(theta, acc, pot)
+
+    def kick_drift(self, pos, vel, acc, dt_kick: float, dt_drift: float):
+        """vel += dt_kick * acc, then pos += dt_drift * vel (in place, float32 [n, 3] device tensors)."""
+        import torch
+        for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+            _require(t, torch.float32, (3,), self.device, name)
+        if not (pos.shape[0] == vel.shape[0] == acc.shape[0]):
+            raise ValueError("pos, vel and acc sizes differ")
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_kick_drift(self.handle, pos.data_ptr(), vel.data_ptr(), acc.data_ptr(),
+                                         int(pos.shape[0]), float(dt_kick), float(dt_drift)))
+
+    def leapfrog(self, pos, vel, mass, theta: float, dt: float, nsteps: int, log_every: int = 0,
+                 acc=None, pot=None):
+        """nsteps kick-drift-kick steps with shared time step dt (pos and vel updated in place).
+        Returns (acc, pot, log): the forces at the final positions and the float64 energy log,
+        rows (t, T, W) at step 0 and every log_every steps (empty when log_every == 0)."""
+        import numpy as np
+        import torch
+        n = int(mass.shape[0])
+        _require(pos, torch.float32, (3,), self.device, "pos")
+        _require(vel, torch.float32, (3,), self.device, "vel")
+        _require(mass, torch.float32, (), self.device, "mass")
+        if pos.shape[0] != n or vel.shape[0] != n:
+            raise ValueError("pos, vel and mass sizes differ")
+        if acc is None:
+            acc = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        if pot is None:
+            pot = torch.empty((n,), dtype=torch.float32, device=self.device)
+        cap = int(nsteps) // int(log_every) + 1 if log_every > 0 else 0
+        log = np.zeros((max(cap, 1), 3), dtype=np.float64)
+        nlog = C.c_int(0)
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_leapfrog(self.handle, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), n,
+                                       float(theta), float(dt), int(nsteps), int(log_every), acc.data_ptr(),
+                                       pot.data_ptr(), log.ctypes.data, cap, C.byref(nlog)))
+        self.n = n
+        self._keep = (pos, mass)
+        self._out = (acc, pot)
+        return acc, pot, log[:nlog.value]
 
     def sync(self):
         _check(lib().mibh_sync(self.handle))

@@ -121,6 +121,28 @@ mibh_status mibh_compute_multipoles(mibh_ctx *ctx);
  * Errors: EINVAL (theta not finite or <= 0, null outputs), ESTATE. */
 mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float *d_pot);
 
+/* Refit (block time steps, the paper's Discussion section: between
+ * rebuilds only the multipole moments are recomputed).  The particles of the
+ * last build_tree take new positions and masses d_pos [n][3], d_mass [n]
+ * (input order, the same n particles); the sorted order, cells and groups
+ * are kept and the particles are moved into that order again.  Call
+ * compute_multipoles next: it recomputes every cell's moments, delta and
+ * l' (MIBH_EXPORT_LSIDE), so a cell whose particles left its cube is opened
+ * from further away.  Non-finite input or negative masses are reported by the
+ * next synchronising call.  Errors: ESTATE before build_tree, EINVAL. */
+mibh_status mibh_refit(mibh_ctx *ctx, const float *d_pos, const float *d_mass);
+
+/* compute_forces for the groups that hold at least one particle with
+ * d_active[i] != 0 (uint8 [n], input order, device memory): the walk visits
+ * only those groups (the paper's block time steps, Results section: the
+ * traverse time falls with the number of active particles).  acc and pot are
+ * written for every particle of a visited group and left untouched for the
+ * others; MIBH_EXPORT_COUNTS is updated for the visited groups only, and
+ * MIBH_EXPORT_QUEUE lists the visited groups first, in Morton order.
+ * Errors: as compute_forces, EINVAL for a null mask. */
+mibh_status mibh_compute_forces_active(mibh_ctx *ctx, float theta, const uint8_t *d_active, float *d_acc,
+                                       float *d_pot);
+
 /* build_tree + compute_multipoles + compute_forces in order. */
 mibh_status mibh_forces(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n,
                         float theta, float *d_acc, float *d_pot);
@@ -205,11 +227,16 @@ mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float
  *                                         with MIBH_ORDER_ESTIMATOR
  *   MIBH_EXPORT_QUEUE   uint32 [ngroups]  group indices in the order the last walk took them
  *                                         (ESTATE when that walk used Morton order)
+ *   MIBH_EXPORT_LSIDE   float64 [ncells]  l' = max(cell side, 2 * largest per-axis distance of
+ *                                         a particle from the cell's geometric centre); the
+ *                                         MAC uses r_open = l'/theta + delta (l' = side unless
+ *                                         particles moved out of their cells: mibh_refit)
  * Synchronises (it reads the current sizes).  Errors: EINVAL, ESTATE. */
 enum {
     MIBH_EXPORT_KEYS = 0, MIBH_EXPORT_PERM, MIBH_EXPORT_CELLS, MIBH_EXPORT_GROUPS,
     MIBH_EXPORT_COUNTS, MIBH_EXPORT_MULTIPOLES, MIBH_EXPORT_DELTA, MIBH_EXPORT_MAC,
-    MIBH_EXPORT_QUAD, MIBH_EXPORT_SPOS, MIBH_EXPORT_FEATURES, MIBH_EXPORT_PREDICTIONS, MIBH_EXPORT_QUEUE
+    MIBH_EXPORT_QUAD, MIBH_EXPORT_SPOS, MIBH_EXPORT_FEATURES, MIBH_EXPORT_PREDICTIONS, MIBH_EXPORT_QUEUE,
+    MIBH_EXPORT_LSIDE
 };
 mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes);
 mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes);

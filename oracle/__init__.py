@@ -55,6 +55,10 @@ def lib():
         L.orc_mac_prep.restype = C.c_int
         L.orc_walk.argtypes = [P, C.c_float, C.c_double, C.c_double, i64, i64, C.c_int]
         L.orc_walk.restype = C.c_int
+        L.orc_refit.argtypes = [P, P, P]
+        L.orc_refit.restype = C.c_int
+        L.orc_walk_list.argtypes = [P, C.c_float, C.c_double, C.c_double, P, i64, C.c_int]
+        L.orc_walk_list.restype = C.c_int
         L.orc_group_lists.argtypes = [P, i64, P, i64, P, i64, P, P]
         L.orc_group_lists.restype = C.c_int
         L.orc_unsort.argtypes = [P]
@@ -74,6 +78,7 @@ def lib():
         for name in ("orc_lo", "orc_keys", "orc_perm", "orc_level", "orc_first", "orc_count",
                      "orc_child_first", "orc_nchild", "orc_parent", "orc_gfirst", "orc_gcount",
                      "orc_gcell", "orc_glevel", "orc_M", "orc_com", "orc_S", "orc_Q", "orc_delta",
+                     "orc_bmin", "orc_bmax", "orc_lside",
                      "orc_com32", "orc_r2open", "orc_n_pc", "orc_n_pp", "orc_sacc", "orc_spot",
                      "orc_acc", "orc_pot"):
             getattr(L, name).argtypes = [P]
@@ -170,7 +175,30 @@ class Tree:
             "S": self._arr("orc_S", np.float64, 6 * nc).reshape(nc, 6),
             "Q": self._arr("orc_Q", np.float64, 6 * nc).reshape(nc, 6),
             "delta": self._arr("orc_delta", np.float64, nc),
+            "bmin": self._arr("orc_bmin", np.float32, 3 * nc).reshape(nc, 3),
+            "bmax": self._arr("orc_bmax", np.float32, 3 * nc).reshape(nc, 3),
+            "lside": self._arr("orc_lside", np.float64, nc),
         }
+
+    def refit(self, pos, mass):
+        """New positions and masses (input order) for the same particles; the
+        sorted order, cells and groups stay, the multipoles are recomputed."""
+        self._pos = _f32(pos).reshape(-1, 3)
+        self._mass = _f32(mass).reshape(-1)
+        if self._pos.shape[0] != self.n or self._mass.shape[0] != self.n:
+            raise ValueError("refit needs the same number of particles")
+        st = lib().orc_refit(self._t, _ptr(self._pos), _ptr(self._mass))
+        if st != 0:
+            raise OracleError(f"orc_refit failed with status {st}")
+
+    def walk_groups(self, theta: float, groups, eps2: float = 0.0, G: float = 1.0, nthreads: int = 0):
+        """Walk only the listed groups; the other groups' results are left as they were."""
+        gl = np.ascontiguousarray(groups, dtype=np.int64)
+        st = lib().orc_walk_list(self._t, C.c_float(theta), eps2, G, _ptr(gl), gl.shape[0], nthreads)
+        if st != 0:
+            raise OracleError(f"orc_walk_list failed with status {st}")
+        self.theta = theta
+        lib().orc_unsort(self._t)
 
     def mac_prep(self, theta: float):
         st = lib().orc_mac_prep(self._t, C.c_float(theta))

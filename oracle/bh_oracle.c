@@ -27,9 +27,15 @@
  *     grouping of Barnes 1990, named in the Results section): a cell is
  *     accepted for a group iff the squared distance from the group's
  *     bounding box to the cell's centre of mass exceeds r_open^2 with
- *     r_open = l/theta + delta (l: cell side, delta: distance from the centre
- *     of mass to the geometric centre); equality opens; every ancestor-or-self
- *     of the group's own cell is opened.  The predicate is evaluated in
+ *     r_open = l'/theta + delta (l' = max(l, 2 * the largest per-axis distance
+ *     of the cell's particles from its geometric centre), l: cell side,
+ *     delta: distance from the centre of mass to the geometric centre; l' = l
+ *     for a freshly built tree, whose cells contain their particles);
+ *     equality opens; every ancestor-or-self of the group's own cell is
+ *     opened.
+ *   - refit (block time steps, Discussion section): the tree of the last
+ *     build is kept, its particles take new positions in the same sorted
+ *     order and the multipoles, l' and delta are recomputed;  The predicate is evaluated in
  *     float32 with a fixed operation order so that any implementation can
  *     reproduce the same interaction sets bit for bit;
  *   - interactions: float64 here, G and Plummer softening eps2 as parameters,
@@ -75,6 +81,8 @@ typedef struct {
     int *glevel;
     /* multipoles */
     double *M, *com, *S, *Q, *delta; /* com [c][3], S and Q [c][6]: xx yy zz xy xz yz */
+    float *bmin, *bmax;              /* per cell: bounding box of its particles [c][3] */
+    double *lside;                   /* per cell: l' = max(l, 2 * reach from the geometric centre) */
     /* MAC data for the last theta */
     float *com32, *r2open;
     /* per-group list sizes for the last walk */
@@ -114,6 +122,7 @@ void orc_free(orc_tree *t) {
     free(t->nchild); free(t->parent);
     free(t->gfirst); free(t->gcount); free(t->gcell); free(t->glevel);
     free(t->M); free(t->com); free(t->S); free(t->Q); free(t->delta);
+    free(t->bmin); free(t->bmax); free(t->lside);
     free(t->com32); free(t->r2open); free(t->n_pc); free(t->n_pp);
     free(t->sacc); free(t->spot); free(t->acc); free(t->pot);
     free(t);
@@ -321,7 +330,10 @@ static void cell_centre(const orc_tree *t, int64_t c, double centre[3], double *
  *   S   = sum fma(m*d_a, d_b, .), d = x - com            (leaf)
  *   S   = sum (S_c + (M_c*e_a)*e_b), e = com_c - com     (internal)
  *   Q   = 3 S - tr(S) I,  tr(S) = (Sxx + Syy) + Szz
- *   delta = sqrt((dx*dx + dy*dy) + dz*dz), d = com - centre. */
+ *   delta = sqrt((dx*dx + dy*dy) + dz*dz), d = com - centre
+ *   box = float32 min/max of the cell's particles (children's boxes for an
+ *         internal cell), reach = max_a max(centre_a - min_a, max_a - centre_a),
+ *   l'  = max(l, 2 reach). */
 static void compute_multipoles(orc_tree *t) {
     static const int IA[6] = {0, 1, 2, 0, 0, 1}, IB[6] = {0, 1, 2, 1, 2, 2};
     for (int64_t c = t->ncells - 1; c >= 0; c--) {
@@ -329,8 +341,16 @@ static void compute_multipoles(orc_tree *t) {
         cell_centre(t, c, centre, &l);
         double M = 0.0, cm[3] = {0, 0, 0}, S[6] = {0, 0, 0, 0, 0, 0};
         double *com = &t->com[3 * c];
+        float *bn = &t->bmin[3 * c], *bx = &t->bmax[3 * c];
         if (t->nchild[c] == 0) {
             int64_t b = t->first[c], e = t->first[c] + t->count[c];
+            for (int a = 0; a < 3; a++) bn[a] = bx[a] = t->sposf[3 * b + a];
+            for (int64_t j = b; j < e; j++)
+                for (int a = 0; a < 3; a++) {
+                    float v = t->sposf[3 * j + a];
+                    if (v < bn[a]) bn[a] = v;
+                    if (v > bx[a]) bx[a] = v;
+                }
             for (int64_t j = b; j < e; j++) {
                 M = M + t->smass[j];
                 for (int a = 0; a < 3; a++) cm[a] = fma(t->smass[j], t->spos[3 * j + a], cm[a]);
@@ -343,6 +363,15 @@ static void compute_multipoles(orc_tree *t) {
             }
         } else {
             int64_t cb = t->child_first[c], ce = cb + t->nchild[c];
+            for (int a = 0; a < 3; a++) {
+                bn[a] = t->bmin[3 * cb + a];
+                bx[a] = t->bmax[3 * cb + a];
+            }
+            for (int64_t ch = cb; ch < ce; ch++)
+                for (int a = 0; a < 3; a++) {
+                    if (t->bmin[3 * ch + a] < bn[a]) bn[a] = t->bmin[3 * ch + a];
+                    if (t->bmax[3 * ch + a] > bx[a]) bx[a] = t->bmax[3 * ch + a];
+                }
             for (int64_t ch = cb; ch < ce; ch++) {
                 M = M + t->M[ch];
                 for (int a = 0; a < 3; a++) cm[a] = fma(t->M[ch], t->com[3 * ch + a], cm[a]);
@@ -364,6 +393,13 @@ static void compute_multipoles(orc_tree *t) {
         for (int s = 3; s < 6; s++) t->Q[6 * c + s] = 3.0 * S[s];
         double dx = com[0] - centre[0], dy = com[1] - centre[1], dz = com[2] - centre[2];
         t->delta[c] = sqrt((dx * dx + dy * dy) + dz * dz);
+        double reach = 0.0;
+        for (int a = 0; a < 3; a++) {
+            double lo_d = centre[a] - (double)bn[a], hi_d = (double)bx[a] - centre[a];
+            if (lo_d > reach) reach = lo_d;
+            if (hi_d > reach) reach = hi_d;
+        }
+        t->lside[c] = 2.0 * reach > l ? 2.0 * reach : l;
     }
 }
 
@@ -419,6 +455,9 @@ int orc_build(orc_tree *t, const float *pos, const float *mass, int64_t n, int n
     t->S = xcalloc(6 * nc, sizeof(double));
     t->Q = xcalloc(6 * nc, sizeof(double));
     t->delta = xcalloc(nc, sizeof(double));
+    t->bmin = xcalloc(3 * nc, sizeof(float));
+    t->bmax = xcalloc(3 * nc, sizeof(float));
+    t->lside = xcalloc(nc, sizeof(double));
     t->com32 = xcalloc(3 * nc, sizeof(float));
     t->r2open = xcalloc(nc, sizeof(float));
     t->n_pc = xcalloc(t->ngroups, sizeof(int64_t));
@@ -428,8 +467,33 @@ int orc_build(orc_tree *t, const float *pos, const float *mass, int64_t n, int n
     t->acc = xcalloc(3 * n, sizeof(double));
     t->pot = xcalloc(n, sizeof(double));
     if (!t->M || !t->com || !t->S || !t->Q || !t->delta || !t->com32 || !t->r2open ||
+        !t->bmin || !t->bmax || !t->lside ||
         !t->n_pc || !t->n_pp || !t->sacc || !t->spot || !t->acc || !t->pot)
         return ORC_ENOMEM;
+    compute_multipoles(t);
+    return ORC_OK;
+}
+
+/* Refit (block time steps): the particles of the last build take new
+ * positions and masses (input order, same particles); the sorted order,
+ * cells and groups stay, the moved properties and the multipoles are
+ * recomputed. */
+int orc_refit(orc_tree *t, const float *pos, const float *mass) {
+    if (!t || !t->keys || !pos || !mass) return ORC_EINVAL;
+    for (int64_t i = 0; i < 3 * t->n; i++)
+        if (!isfinite(pos[i])) return ORC_ENONFINITE;
+    for (int64_t i = 0; i < t->n; i++) {
+        if (!isfinite(mass[i])) return ORC_ENONFINITE;
+        if (mass[i] < 0.0f) return ORC_EINVAL;
+    }
+    for (int64_t k = 0; k < t->n; k++) {
+        int64_t i = t->perm[k];
+        for (int a = 0; a < 3; a++) {
+            t->sposf[3 * k + a] = pos[3 * i + a];
+            t->spos[3 * k + a] = (double)pos[3 * i + a];
+        }
+        t->smass[k] = (double)mass[i];
+    }
     compute_multipoles(t);
     return ORC_OK;
 }
@@ -438,14 +502,13 @@ int orc_build(orc_tree *t, const float *pos, const float *mass, int64_t n, int n
 /* Step 8: MAC data for one theta                                       */
 /* ------------------------------------------------------------------ */
 
-/* r_open = l/theta + delta in float64 (theta is the float32 input widened),
+/* r_open = l'/theta + delta in float64 (theta is the float32 input widened),
  * stored squared and rounded to float32; the centre of mass is rounded to
  * float32 for the float32 predicate. */
 int orc_mac_prep(orc_tree *t, float theta) {
     if (!(theta > 0.0f) || !isfinite(theta)) return ORC_EINVAL;
     for (int64_t c = 0; c < t->ncells; c++) {
-        double l = ldexp(1.0, t->k - t->level[c]);
-        double ro = l / (double)theta + t->delta[c];
+        double ro = t->lside[c] / (double)theta + t->delta[c];
         t->r2open[c] = (float)(ro * ro);
         for (int a = 0; a < 3; a++) t->com32[3 * c + a] = (float)t->com[3 * c + a];
     }
@@ -551,15 +614,35 @@ static void pp_interaction(const double xj[3], double mj, const double x[3], dou
     *phi -= G * mj * rinv;
 }
 
-/* Walk groups [g_begin, g_end) with nthreads threads (<= 0: runtime default),
- * after orc_mac_prep(theta).  Fills n_pc/n_pp for those groups and the sorted
- * accelerations and potentials of their particles. */
-int orc_walk(orc_tree *t, float theta, double eps2, double G, int64_t g_begin, int64_t g_end,
-             int nthreads) {
-    int st = orc_mac_prep(t, theta);
-    if (st) return st;
-    if (g_begin < 0) g_begin = 0;
-    if (g_end > t->ngroups) g_end = t->ngroups;
+/* Lists and interactions of group g (after orc_mac_prep): fills n_pc/n_pp of
+ * the group and the sorted accelerations and potentials of its particles. */
+static int walk_group(orc_tree *t, int64_t g, double eps2, double G, vec_t *stack, vec_t *pc, vec_t *pp) {
+    if (group_lists(t, g, stack, pc, pp)) return ORC_ENOMEM;
+    int64_t npp = 0;
+    for (int64_t k = 0; k < pp->n; k++) npp += t->count[pp->v[k]];
+    t->n_pc[g] = pc->n;
+    t->n_pp[g] = npp;
+    for (int64_t i = t->gfirst[g]; i < t->gfirst[g] + t->gcount[g]; i++) {
+        const double *x = &t->spos[3 * i];
+        double a[3] = {0, 0, 0}, phi = 0.0;
+        for (int64_t k = 0; k < pc->n; k++) pc_interaction(t, pc->v[k], x, eps2, G, a, &phi);
+        for (int64_t k = 0; k < pp->n; k++) {
+            int64_t c = pp->v[k];
+            for (int64_t j = t->first[c]; j < t->first[c] + t->count[c]; j++) {
+                if (j == i) continue;
+                pp_interaction(&t->spos[3 * j], t->smass[j], x, eps2, G, a, &phi);
+            }
+        }
+        for (int d = 0; d < 3; d++) t->sacc[3 * i + d] = a[d];
+        t->spot[i] = phi;
+    }
+    return ORC_OK;
+}
+
+/* Walk the groups glist[0..ng) (glist NULL: groups g_begin + 0..ng) with
+ * nthreads threads (<= 0: runtime default), after orc_mac_prep. */
+static int walk_groups(orc_tree *t, double eps2, double G, const int64_t *glist, int64_t g_begin, int64_t ng,
+                       int nthreads) {
     int err = ORC_OK;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -570,30 +653,34 @@ int orc_walk(orc_tree *t, float theta, double eps2, double G, int64_t g_begin, i
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 16)
 #endif
-        for (int64_t g = g_begin; g < g_end; g++) {
-            if (group_lists(t, g, &stack, &pc, &pp)) { err = ORC_ENOMEM; continue; }
-            int64_t npp = 0;
-            for (int64_t k = 0; k < pp.n; k++) npp += t->count[pp.v[k]];
-            t->n_pc[g] = pc.n;
-            t->n_pp[g] = npp;
-            for (int64_t i = t->gfirst[g]; i < t->gfirst[g] + t->gcount[g]; i++) {
-                const double *x = &t->spos[3 * i];
-                double a[3] = {0, 0, 0}, phi = 0.0;
-                for (int64_t k = 0; k < pc.n; k++) pc_interaction(t, pc.v[k], x, eps2, G, a, &phi);
-                for (int64_t k = 0; k < pp.n; k++) {
-                    int64_t c = pp.v[k];
-                    for (int64_t j = t->first[c]; j < t->first[c] + t->count[c]; j++) {
-                        if (j == i) continue;
-                        pp_interaction(&t->spos[3 * j], t->smass[j], x, eps2, G, a, &phi);
-                    }
-                }
-                for (int d = 0; d < 3; d++) t->sacc[3 * i + d] = a[d];
-                t->spot[i] = phi;
-            }
+        for (int64_t k = 0; k < ng; k++) {
+            int64_t g = glist ? glist[k] : g_begin + k;
+            if (walk_group(t, g, eps2, G, &stack, &pc, &pp)) err = ORC_ENOMEM;
         }
         free(stack.v); free(pc.v); free(pp.v);
     }
     return err;
+}
+
+/* Walk groups [g_begin, g_end), after MAC data for theta. */
+int orc_walk(orc_tree *t, float theta, double eps2, double G, int64_t g_begin, int64_t g_end,
+             int nthreads) {
+    int st = orc_mac_prep(t, theta);
+    if (st) return st;
+    if (g_begin < 0) g_begin = 0;
+    if (g_end > t->ngroups) g_end = t->ngroups;
+    if (g_end <= g_begin) return ORC_OK;
+    return walk_groups(t, eps2, G, NULL, g_begin, g_end - g_begin, nthreads);
+}
+
+/* Walk the listed groups (each at most once; any order). */
+int orc_walk_list(orc_tree *t, float theta, double eps2, double G, const int64_t *glist, int64_t ng,
+                  int nthreads) {
+    int st = orc_mac_prep(t, theta);
+    if (st) return st;
+    for (int64_t k = 0; k < ng; k++)
+        if (glist[k] < 0 || glist[k] >= t->ngroups) return ORC_EINVAL;
+    return walk_groups(t, eps2, G, glist, 0, ng, nthreads);
 }
 
 /* Interaction lists of one group (after orc_mac_prep), for brute-force checks:
@@ -694,6 +781,9 @@ const double *orc_com(const orc_tree *t) { return t->com; }
 const double *orc_S(const orc_tree *t) { return t->S; }
 const double *orc_Q(const orc_tree *t) { return t->Q; }
 const double *orc_delta(const orc_tree *t) { return t->delta; }
+const float *orc_bmin(const orc_tree *t) { return t->bmin; }
+const float *orc_bmax(const orc_tree *t) { return t->bmax; }
+const double *orc_lside(const orc_tree *t) { return t->lside; }
 const float *orc_com32(const orc_tree *t) { return t->com32; }
 const float *orc_r2open(const orc_tree *t) { return t->r2open; }
 const int64_t *orc_n_pc(const orc_tree *t) { return t->n_pc; }

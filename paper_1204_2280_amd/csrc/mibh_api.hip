@@ -13,6 +13,9 @@
 
 using namespace mibh;
 
+// queue mode of a walk over the groups holding an active particle (internal)
+constexpr int ORDER_ACTIVE = 3;
+
 struct mibh_ctx {
     mibh_params p;
     int64_t n_max;
@@ -127,6 +130,8 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.topo = (uint4 *)take(16 * cap_cells);
     t.mp = (double *)take(80 * cap_cells);
     t.delta = (double *)take(8 * cap_cells);
+    t.cbox = (float *)take(24 * cap_cells);
+    t.lside = (double *)take(8 * cap_cells);
     t.cmac = (float4 *)take(16 * cap_cells);
     t.ceval = (float4 *)take(32 * cap_cells);
     t.groups = (uint2 *)take(8 * n);
@@ -328,25 +333,29 @@ mibh_status mibh_compute_multipoles(mibh_ctx *ctx) {
     return MIBH_OK;
 }
 
-mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float *d_pot) {
+// The force step on the current tree: every group (active == nullptr) or the
+// groups holding a particle with active[input index] != 0.
+static mibh_status forces_impl(mibh_ctx *ctx, float theta, const uint8_t *d_active, float *d_acc, float *d_pot) {
     mibh_status st = check_ctx(ctx);
     if (st) return st;
     if (ctx->state < 2) return fail(MIBH_ESTATE, "compute_forces before compute_multipoles");
     if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
     if (!d_acc || !d_pot) return fail(MIBH_EINVAL, "null output pointer");
-    const double inv_theta = 1.0 / (double)theta;
+
     if ((st = mark(ctx, MIBH_STAGE_MULTIPOLES))) return st;  // no-op after compute_multipoles in this step
-    HIP_TRY(launch_mac_prep(ctx->b, (unsigned)ctx->nsys, inv_theta, ctx->stream), "mac_prep");
-    int mode = ctx->order;
+    HIP_TRY(launch_mac_prep(ctx->b, (unsigned)ctx->nsys, (double)theta, ctx->stream), "mac_prep");
+    int mode = d_active ? ORDER_ACTIVE : ctx->order;
     if (mode == MIBH_ORDER_EXACT && !ctx->counts_valid) mode = MIBH_ORDER_MORTON;  // no walk of this tree yet
     if (mode == MIBH_ORDER_ESTIMATOR) {
         HIP_TRY(launch_features(ctx->b, theta, ctx->b.feat, ctx->stream), "features");
         HIP_TRY(launch_mlp_forward(ctx->est_w16, ctx->b.feat, 0, ctx->b.hdr, ctx->b.pred, ctx->stream), "estimator");
     }
-    if (mode != MIBH_ORDER_MORTON) HIP_TRY(launch_queue_order(ctx->b, mode, ctx->stream), "queue order");
+    if (mode != MIBH_ORDER_MORTON)
+        HIP_TRY(launch_queue_order(ctx->b, mode, d_active, (unsigned)ctx->nsys, ctx->stream), "queue order");
     if ((st = mark(ctx, MIBH_STAGE_MACPREP))) return st;
     HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, (unsigned)ctx->nsys, ctx->p.eps2, ctx->p.G, ctx->p.precision,
-                        mode == MIBH_ORDER_MORTON ? nullptr : ctx->b.qorder, d_acc, d_pot, ctx->stream),
+                        mode == MIBH_ORDER_MORTON ? nullptr : ctx->b.qorder,
+                        d_active ? ctx->b.ohist + ORDER_BLOCKS : nullptr, d_acc, d_pot, ctx->stream),
             "walk");
     ctx->last_order = mode;
     if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;
@@ -358,6 +367,31 @@ mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float 
     ctx->acc = d_acc;
     ctx->pot = d_pot;
     ctx->state = 3;
+    return MIBH_OK;
+}
+
+mibh_status mibh_compute_forces(mibh_ctx *ctx, float theta, float *d_acc, float *d_pot) {
+    return forces_impl(ctx, theta, nullptr, d_acc, d_pot);
+}
+
+mibh_status mibh_compute_forces_active(mibh_ctx *ctx, float theta, const uint8_t *d_active, float *d_acc,
+                                       float *d_pot) {
+    if (!d_active) return fail(MIBH_EINVAL, "null active mask");
+    return forces_impl(ctx, theta, d_active, d_acc, d_pot);
+}
+
+mibh_status mibh_refit(mibh_ctx *ctx, const float *d_pos, const float *d_mass) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->state < 1) return fail(MIBH_ESTATE, "refit before build_tree");
+    if (!d_pos || !d_mass) return fail(MIBH_EINVAL, "null input pointer");
+    if ((st = mark(ctx, MIBH_STAGE_SORT))) return st;  // a refit has no sorting or tree construction
+    HIP_TRY(launch_pack(ctx->b, d_pos, d_mass, (unsigned)ctx->n, ctx->stream), "pack");
+    HIP_TRY(launch_reorder(ctx->b, (unsigned)ctx->n, (unsigned)ctx->nsys, ctx->stream), "reorder");
+    if ((st = mark(ctx, MIBH_STAGE_BUILD))) return st;
+    ctx->pos = d_pos;
+    ctx->mass = d_mass;
+    ctx->state = 1;
     return MIBH_OK;
 }
 
@@ -519,6 +553,7 @@ mibh_status mibh_export_bytes(mibh_ctx *ctx, int what, size_t *bytes) {
         case MIBH_EXPORT_FEATURES: *bytes = 4 * (size_t)MLP_IN * ng; break;
         case MIBH_EXPORT_PREDICTIONS: *bytes = 4 * ng; break;
         case MIBH_EXPORT_QUEUE: *bytes = 4 * ng; break;
+        case MIBH_EXPORT_LSIDE: *bytes = 8 * nc; break;
         default: return fail(MIBH_EINVAL, "unknown export %d", what);
     }
     return MIBH_OK;
@@ -534,7 +569,8 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
         return fail(MIBH_ESTATE, "export of walk data before compute_forces");
     if (what == MIBH_EXPORT_QUEUE && ctx->last_order == MIBH_ORDER_MORTON)
         return fail(MIBH_ESTATE, "the last walk took the groups in Morton order");
-    if ((what == MIBH_EXPORT_MULTIPOLES || what == MIBH_EXPORT_DELTA || what == MIBH_EXPORT_QUAD) &&
+    if ((what == MIBH_EXPORT_MULTIPOLES || what == MIBH_EXPORT_DELTA || what == MIBH_EXPORT_QUAD ||
+         what == MIBH_EXPORT_LSIDE) &&
         ctx->state < 2)
         return fail(MIBH_ESTATE, "export of multipoles before compute_multipoles");
     const void *src = nullptr;
@@ -552,6 +588,7 @@ mibh_status mibh_export(mibh_ctx *ctx, int what, void *d_dst, size_t bytes) {
         case MIBH_EXPORT_FEATURES: src = ctx->b.feat; break;
         case MIBH_EXPORT_PREDICTIONS: src = ctx->b.pred; break;
         case MIBH_EXPORT_QUEUE: src = ctx->b.qorder; break;
+        case MIBH_EXPORT_LSIDE: src = ctx->b.lside; break;
     }
     if (need) HIP_TRY(hipMemcpyAsync(d_dst, src, need, hipMemcpyDeviceToDevice, ctx->stream), "hipMemcpyAsync(export)");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");

@@ -90,6 +90,8 @@ struct Buffers {
     uint4 *topo;            // cells: first, count, child_first, system<<16 | level<<8 | nchild
     double *mp;             // cells: [10] M, com xyz, S xx yy zz xy xz yz
     double *delta;          // cells: |com - centre|
+    float *cbox;            // cells: [6] bounding box of the cell's particles (min xyz, max xyz)
+    double *lside;          // cells: l' = max(side, 2 * largest per-axis distance of a particle from the centre)
     float4 *cmac;           // cells: com32 xyz, r_open^2
     float4 *ceval;          // cells: [2] (M, Qxx, Qyy, Qzz), (Qxy, Qxz, Qyz, 0)
     uint2 *groups;          // first, system<<16 | level<<8 | count
@@ -125,10 +127,12 @@ inline int sorted_buffer(unsigned nsys) { return nsys > 1 ? (SORT_PASSES + 1) & 
 hipError_t launch_reorder(const Buffers &b, unsigned n, unsigned nsys, hipStream_t s);
 hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, int gcap, hipStream_t s);
 hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s);
-hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double inv_theta, hipStream_t s);
-// order: the queue (NULL: groups in Morton order)
+// theta: the float32 opening angle widened to float64
+hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double theta, hipStream_t s);
+// order: the queue (NULL: groups in Morton order); qlen: device count of queue
+// entries to walk (NULL: every group)
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
-                       const uint32_t *order, float *acc, float *pot, hipStream_t s);
+                       const uint32_t *order, const uint32_t *qlen, float *acc, float *pot, hipStream_t s);
 hipError_t launch_features(const Buffers &b, float theta, float *feat, hipStream_t s);
 hipError_t launch_mlp_forward(const void *w16, const float *x, unsigned rows, const Header *hdr, float *y,
                               hipStream_t s);
@@ -138,8 +142,12 @@ hipError_t launch_mlp_grad(const void *w16, const float *x, const float *target,
 hipError_t launch_adam(float *w32, void *w16, const float *grad, float *m, float *v, int step, float lr,
                        float beta1, float beta2, float eps, hipStream_t s);
 // Writes b.qorder: the groups ordered by work, heaviest first; mode 1: work
-// predicted by the estimator (b.pred), 2: exact counts of the last walk.
-hipError_t launch_queue_order(const Buffers &b, int mode, hipStream_t s);
+// predicted by the estimator (b.pred), 2: exact counts of the last walk; mode
+// 3: groups holding a particle with active[input index] != 0 first (their
+// number, after the call, is b.ohist[ORDER_BLOCKS]), in Morton order.
+hipError_t launch_queue_order(const Buffers &b, int mode, const uint8_t *active, unsigned nsys, hipStream_t s);
+// Packs input (x, y, z, m) into b.ppack and flags non-finite or negative values.
+hipError_t launch_pack(const Buffers &b, const float *pos, const float *mass, unsigned n, hipStream_t s);
 // v <- v + dt_kick a, then (dt_drift != 0) x <- x + dt_drift v, for n particles
 hipError_t launch_kick_drift(float *pos, float *vel, const float *acc, unsigned n, float dt_kick, float dt_drift,
                              hipStream_t s);

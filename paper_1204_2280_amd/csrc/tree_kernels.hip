@@ -281,6 +281,27 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ pos, con
     if (nsys > 1) sys8[i] = (uint8_t)sys;
 }
 
+// Refit input: packs (x, y, z, m) like the keys kernel and records non-finite
+// values and negative masses in the header flags (the build does this in its
+// bounding-box pass).
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ pos, const float *__restrict__ mass,
+                                              unsigned n, Header *__restrict__ hdr, float4 *__restrict__ ppack) {
+    for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const float4 p = make_float4(pos[(size_t)i * 3], pos[(size_t)i * 3 + 1], pos[(size_t)i * 3 + 2], mass[i]);
+        ppack[i] = p;
+        unsigned f = 0;
+        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z) || !isfinite(p.w)) f |= FLAG_NONFINITE;
+        if (p.w < 0.0f) f |= FLAG_NEGMASS;
+        if (f) atomicOr(&hdr->flags, f);
+    }
+}
+
+hipError_t launch_pack(const Buffers &b, const float *pos, const float *mass, unsigned n, hipStream_t s) {
+    const unsigned grid = min((n + 255u) / 256u, 8192u);
+    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, s, pos, mass, n, b.hdr, b.ppack);
+    return hipGetLastError();
+}
+
 hipError_t launch_keys(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, s, pos, mass, n, nsys, b.sys_off, b.cube,
@@ -698,6 +719,12 @@ hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, 
 //   internal: M = sum M_c, com = (sum fma(M_c, com_c, .)) / M,
 //             S_ab = sum (S_c,ab + (M_c e_a) e_b), e = com_c - com
 //   Q = 3 S - tr(S) I, delta = |com - geometric centre|
+//   box = float32 min/max of the cell's particles (children's boxes for an
+//   internal cell); l' = max(l, 2 max_a max(centre_a - min_a, max_a - centre_a)):
+//   the side of the smallest cube about the geometric centre that holds the
+//   particles, never below the cell side.  A freshly built cell holds its
+//   particles, so l' = l; after a refit (particles moved, tree kept) l' grows
+//   with the particles that left their cells.
 // The operation order is fixed and nothing is contracted except the explicit
 // fma calls, so every run gives the same bits.
 // --------------------------------------------------------------------------
@@ -707,8 +734,8 @@ constexpr unsigned LEAF_REGS = 16;  // leaves up to this size are summed from re
 __global__ __launch_bounds__(256) void k_multipole_level(
     int lev, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
     const float4 *__restrict__ spos, const uint64_t *__restrict__ keys, double *__restrict__ mp,
-    double *__restrict__ delta, float4 *__restrict__ cmac, float4 *__restrict__ ceval,
-    unsigned cap_cells) {
+    double *__restrict__ delta, float *__restrict__ cbox, double *__restrict__ lside, float4 *__restrict__ cmac,
+    float4 *__restrict__ ceval, unsigned cap_cells) {
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
@@ -728,6 +755,7 @@ __global__ __launch_bounds__(256) void k_multipole_level(
         }
         double M = 0.0, cm[3] = {0.0, 0.0, 0.0}, com[3];
         double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        float bn[3], bx[3];
         if (nch == 0 && t.y <= LEAF_REGS) {
             // a leaf of up to LEAF_REGS particles: all loads in flight at once,
             // both passes from registers (same operations in the same order)
@@ -735,6 +763,20 @@ __global__ __launch_bounds__(256) void k_multipole_level(
 #pragma unroll
             for (int j = 0; j < LEAF_REGS; j++)
                 pr[j] = (unsigned)j < t.y ? spos[t.x + j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            bn[0] = bx[0] = pr[0].x;
+            bn[1] = bx[1] = pr[0].y;
+            bn[2] = bx[2] = pr[0].z;
+#pragma unroll
+            for (int j = 1; j < LEAF_REGS; j++) {
+                if ((unsigned)j < t.y) {
+                    bn[0] = fminf(bn[0], pr[j].x);
+                    bx[0] = fmaxf(bx[0], pr[j].x);
+                    bn[1] = fminf(bn[1], pr[j].y);
+                    bx[1] = fmaxf(bx[1], pr[j].y);
+                    bn[2] = fminf(bn[2], pr[j].z);
+                    bx[2] = fmaxf(bx[2], pr[j].z);
+                }
+            }
 #pragma unroll
             for (int j = 0; j < LEAF_REGS; j++) {
                 if ((unsigned)j < t.y) {
@@ -761,8 +803,20 @@ __global__ __launch_bounds__(256) void k_multipole_level(
                 }
             }
         } else if (nch == 0) {
+            {
+                const float4 p0 = spos[t.x];
+                bn[0] = bx[0] = p0.x;
+                bn[1] = bx[1] = p0.y;
+                bn[2] = bx[2] = p0.z;
+            }
             for (unsigned j = t.x; j < t.x + t.y; j++) {
                 const float4 p = spos[j];
+                bn[0] = fminf(bn[0], p.x);
+                bx[0] = fmaxf(bx[0], p.x);
+                bn[1] = fminf(bn[1], p.y);
+                bx[1] = fmaxf(bx[1], p.y);
+                bn[2] = fminf(bn[2], p.z);
+                bx[2] = fmaxf(bx[2], p.z);
                 const double m = (double)p.w;
                 M = M + m;
                 cm[0] = fma(m, (double)p.x, cm[0]);
@@ -782,6 +836,16 @@ __global__ __launch_bounds__(256) void k_multipole_level(
                 S[5] = fma(m * dy, dz, S[5]);
             }
         } else {
+            for (int a = 0; a < 3; a++) {
+                bn[a] = cbox[6 * (size_t)t.z + a];
+                bx[a] = cbox[6 * (size_t)t.z + 3 + a];
+            }
+            for (unsigned ch = t.z + 1; ch < t.z + nch; ch++) {
+                for (int a = 0; a < 3; a++) {
+                    bn[a] = fminf(bn[a], cbox[6 * (size_t)ch + a]);
+                    bx[a] = fmaxf(bx[a], cbox[6 * (size_t)ch + 3 + a]);
+                }
+            }
             for (unsigned ch = t.z; ch < t.z + nch; ch++) {
                 const double *p = mp + 10 * (size_t)ch;
                 M = M + p[0];
@@ -812,6 +876,14 @@ __global__ __launch_bounds__(256) void k_multipole_level(
         const double Q0 = 3.0 * S[0] - tr, Q1 = 3.0 * S[1] - tr, Q2 = 3.0 * S[2] - tr;
         const double dx = com[0] - centre[0], dy = com[1] - centre[1], dz = com[2] - centre[2];
         delta[c] = sqrt((dx * dx + dy * dy) + dz * dz);
+        double reach = 0.0;
+        for (int a = 0; a < 3; a++) {
+            reach = fmax(reach, centre[a] - (double)bn[a]);
+            reach = fmax(reach, (double)bx[a] - centre[a]);
+            cbox[6 * (size_t)c + a] = bn[a];
+            cbox[6 * (size_t)c + 3 + a] = bx[a];
+        }
+        lside[c] = fmax(l, 2.0 * reach);
         cmac[c] = make_float4((float)com[0], (float)com[1], (float)com[2], 0.0f);
         ceval[2 * (size_t)c] = make_float4((float)M, (float)Q0, (float)Q1, (float)Q2);
         ceval[2 * (size_t)c + 1] =
@@ -823,33 +895,31 @@ hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s) {
     const unsigned grid = min((b.cap_cells + 255u) / 256u, 2048u);
     for (int lev = KEY_LEVELS; lev >= 0; lev--)
         hipLaunchKernelGGL(k_multipole_level, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.cube, b.topo, b.spos,
-                           b.keys[sorted_buffer(nsys)], b.mp, b.delta, b.cmac, b.ceval, b.cap_cells);
+                           b.keys[sorted_buffer(nsys)], b.mp, b.delta, b.cbox, b.lside, b.cmac, b.ceval,
+                           b.cap_cells);
     return hipGetLastError();
 }
 
-// r_open = l/theta + delta with l/theta = 2^(k - level) * (1/theta) (exact
-// scaling of the host-rounded reciprocal), squared in float64, rounded once.
-__global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr, const SysCube *__restrict__ cube,
-                                                  const uint4 *__restrict__ topo,
-                                                  const double *__restrict__ delta, double inv_theta,
+// r_open = l'/theta + delta in float64 (a correctly rounded division; for a
+// fresh cell l' = 2^(k - level) and the quotient is the exact scaling of
+// fl(1/theta)), squared in float64, rounded once to float32.
+__global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr, const double *__restrict__ lside,
+                                                  const double *__restrict__ delta, double theta,
                                                   float4 *__restrict__ cmac, unsigned cap_cells) {
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
     if (blockIdx.x == 0 && threadIdx.x == 0) hdr->walk_head = 0;  // queue of the walk that follows
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
-        const unsigned w = topo[c].w;
-        const int lev = (int)((w >> 8) & 255u);
-        const int k = cube[w >> 16].k;
-        const double ro = ldexp(inv_theta, k - lev) + delta[c];
+        const double ro = lside[c] / theta + delta[c];
         cmac[c].w = (float)(ro * ro);
     }
 }
 
-hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double inv_theta, hipStream_t s) {
+hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double theta, hipStream_t s) {
     (void)nsys;
     const unsigned grid = min((b.cap_cells + 255u) / 256u, 4096u);
-    hipLaunchKernelGGL(k_mac_prep, dim3(grid), dim3(256), 0, s, b.hdr, b.cube, b.topo, b.delta, inv_theta, b.cmac,
+    hipLaunchKernelGGL(k_mac_prep, dim3(grid), dim3(256), 0, s, b.hdr, b.lside, b.delta, theta, b.cmac,
                        b.cap_cells);
     return hipGetLastError();
 }

@@ -133,6 +133,7 @@ struct WalkArgs {
     uint2 *gcounts;
     uint32_t *wstack;
     const uint32_t *order;   // queue order (NULL: Morton order)
+    const uint32_t *qlen;    // number of queue entries to walk (NULL: all groups)
     unsigned *head;          // queue head
     float *acc, *pot;
     float eps2, G;
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
     // a round (<= 64 * per_round) fits after a flush leaves < 64 entries
     const unsigned per_round = max(1u, (a.pp_cap - 64u) >> 6);  // < 16 since pp_cap <= 1024
     static_assert(WALK_PP_LDS <= 1024, "per-round counts must fit the 4-bit prefix sums");
-    const unsigned ngroups = uniform(a.hdr->ngroups);
+    const unsigned ngroups = a.qlen ? uniform(*a.qlen) : uniform(a.hdr->ngroups);
     for (;;) {
         // Every lane executes the queue atomic (only lane 0 adds 1) so that no
         // lane-dependent branch sits inside this loop: the compiler may split a
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
 }  // namespace
 
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
-                       const uint32_t *order, float *acc, float *pot, hipStream_t s) {
+                       const uint32_t *order, const uint32_t *qlen, float *acc, float *pot, hipStream_t s) {
     (void)n;
     WalkArgs a;
     a.hdr = b.hdr;
@@ -414,6 +415,7 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
     a.gcounts = b.gcounts;
     a.wstack = b.wstack;
     a.order = order;
+    a.qlen = qlen;
     a.head = &b.hdr->walk_head;
     a.acc = acc;
     a.pot = pot;
@@ -445,10 +447,30 @@ constexpr int ORDER_THREADS = 256;
 constexpr int ORDER_SCAN_THREADS = 1024;
 constexpr unsigned ORDER_SKIP = FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP;  // the walk does nothing then
 
-// Queue bucket of group g: 0 for the heaviest work.
-__device__ __forceinline__ unsigned work_bucket(const uint2 *__restrict__ groups, const float *__restrict__ pred,
-                                                const uint2 *__restrict__ counts, int mode, unsigned g) {
-    const float gn = (float)(groups[g].y & 255u);
+struct OrderArgs {
+    const Header *hdr;
+    unsigned n_max;
+    const uint2 *groups;
+    const float *pred;       // mode 1
+    const uint2 *counts;     // mode 2
+    const uint32_t *perm;    // mode 3: sorted position -> input index
+    const uint8_t *active;   // mode 3: per input particle, nonzero = active
+    int mode;
+};
+
+// Queue bucket of group g: 0 for the heaviest work (modes 1, 2), or 0 for a
+// group holding an active particle and 1 otherwise (mode 3).
+__device__ __forceinline__ unsigned work_bucket(const OrderArgs &o, unsigned g) {
+    const uint2 gr = o.groups[g];
+    if (o.mode == 3) {
+        bool any = false;
+        for (unsigned k = gr.x; k < gr.x + (gr.y & 255u); k++) any = any || o.active[o.perm[k]] != 0;
+        return any ? 0u : 1u;
+    }
+    const float gn = (float)(gr.y & 255u);
+    const float *pred = o.pred;
+    const uint2 *counts = o.counts;
+    const int mode = o.mode;
     float l2;
     if (mode == 1) {
         const float p = pred[g];
@@ -468,19 +490,15 @@ __device__ __forceinline__ void order_slice(const Header *hdr, unsigned n_max, u
     *end = min(ng, *beg + chunk);
 }
 
-__global__ __launch_bounds__(ORDER_THREADS) void k_order_hist(const Header *__restrict__ hdr, unsigned n_max,
-                                                              const uint2 *__restrict__ groups,
-                                                              const float *__restrict__ pred,
-                                                              const uint2 *__restrict__ counts, int mode,
-                                                              uint32_t *__restrict__ ohist) {
+__global__ __launch_bounds__(ORDER_THREADS) void k_order_hist(OrderArgs o, uint32_t *__restrict__ ohist) {
     __shared__ unsigned s_h[ORDER_BUCKETS];
-    if (hdr->flags & ORDER_SKIP) return;
+    if (o.hdr->flags & ORDER_SKIP) return;
     const unsigned t = threadIdx.x;
     if (t < ORDER_BUCKETS) s_h[t] = 0;
     __syncthreads();
     unsigned beg, end;
-    order_slice(hdr, n_max, &beg, &end);
-    for (unsigned g = beg + t; g < end; g += ORDER_THREADS) atomicAdd(&s_h[work_bucket(groups, pred, counts, mode, g)], 1u);
+    order_slice(o.hdr, o.n_max, &beg, &end);
+    for (unsigned g = beg + t; g < end; g += ORDER_THREADS) atomicAdd(&s_h[work_bucket(o, g)], 1u);
     __syncthreads();
     if (t < ORDER_BUCKETS) ohist[t * ORDER_BLOCKS + blockIdx.x] = s_h[t];
 }
@@ -515,21 +533,17 @@ __global__ __launch_bounds__(ORDER_SCAN_THREADS) void k_order_scan(uint32_t *__r
     }
 }
 
-__global__ __launch_bounds__(ORDER_THREADS) void k_order_scatter(const Header *__restrict__ hdr, unsigned n_max,
-                                                                 const uint2 *__restrict__ groups,
-                                                                 const float *__restrict__ pred,
-                                                                 const uint2 *__restrict__ counts, int mode,
-                                                                 const uint32_t *__restrict__ ohist,
+__global__ __launch_bounds__(ORDER_THREADS) void k_order_scatter(OrderArgs o, const uint32_t *__restrict__ ohist,
                                                                  uint32_t *__restrict__ order) {
     constexpr int NW = ORDER_THREADS / 64;
     static_assert(NW * ORDER_BUCKETS == 2 * ORDER_THREADS, "two counters per thread to clear");
     __shared__ unsigned s_base[ORDER_BUCKETS];
     __shared__ unsigned s_wcnt[NW][ORDER_BUCKETS];
-    if (hdr->flags & ORDER_SKIP) return;
+    if (o.hdr->flags & ORDER_SKIP) return;
     const unsigned t = threadIdx.x, w = t >> 6;
     if (t < ORDER_BUCKETS) s_base[t] = ohist[t * ORDER_BLOCKS + blockIdx.x];
     unsigned beg, end;
-    order_slice(hdr, n_max, &beg, &end);
+    order_slice(o.hdr, o.n_max, &beg, &end);
     // No branch below depends on the thread alone (see the walk's queue loop).
     for (unsigned t0 = beg; t0 < end; t0 += ORDER_THREADS) {
         (&s_wcnt[0][0])[t] = 0;
@@ -537,7 +551,7 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_order_scatter(const Header *_
         __syncthreads();
         const unsigned g = t0 + t;
         const bool valid = g < end;
-        const unsigned d = valid ? work_bucket(groups, pred, counts, mode, g) : 0u;
+        const unsigned d = valid ? work_bucket(o, g) : 0u;
         // lanes of this wave with the same bucket
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -563,12 +577,19 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_order_scatter(const Header *_
 
 }  // namespace
 
-hipError_t launch_queue_order(const Buffers &b, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_order_hist, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, b.hdr, b.n_max, b.groups, b.pred,
-                       b.gcounts, mode, b.ohist);
+hipError_t launch_queue_order(const Buffers &b, int mode, const uint8_t *active, unsigned nsys, hipStream_t s) {
+    OrderArgs o;
+    o.hdr = b.hdr;
+    o.n_max = b.n_max;
+    o.groups = b.groups;
+    o.pred = b.pred;
+    o.counts = b.gcounts;
+    o.perm = b.vals[sorted_buffer(nsys)];
+    o.active = active;
+    o.mode = mode;
+    hipLaunchKernelGGL(k_order_hist, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, o, b.ohist);
     hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(ORDER_SCAN_THREADS), 0, s, b.ohist);
-    hipLaunchKernelGGL(k_order_scatter, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, b.hdr, b.n_max, b.groups,
-                       b.pred, b.gcounts, mode, b.ohist, b.qorder);
+    hipLaunchKernelGGL(k_order_scatter, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, o, b.ohist, b.qorder);
     return hipGetLastError();
 }
 

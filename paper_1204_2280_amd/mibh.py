@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libmibh.so")
 PLAIN, KAHAN = 0, 1
 EXPORTS = {
     "keys": 0, "perm": 1, "cells": 2, "groups": 3, "counts": 4, "multipoles": 5, "delta": 6,
-    "mac": 7, "quad": 8, "spos": 9, "features": 10, "predictions": 11, "queue": 12,
+    "mac": 7, "quad": 8, "spos": 9, "features": 10, "predictions": 11, "queue": 12, "lside": 13,
 }
 ORDER_MORTON, ORDER_ESTIMATOR, ORDER_EXACT = 0, 1, 2
 MLP_FEATURES, MLP_PARAMS = 8, 4801
@@ -83,6 +83,10 @@ def lib():
                   "mibh_compute_forces", "mibh_forces", "mibh_sync", "mibh_stats", "mibh_energy",
                   "mibh_export_bytes", "mibh_export"):
             getattr(L, f).restype = st
+        L.mibh_refit.argtypes = [P, P, P]
+        L.mibh_refit.restype = st
+        L.mibh_compute_forces_active.argtypes = [P, C.c_float, P, P, P]
+        L.mibh_compute_forces_active.restype = st
         L.mibh_kick_drift.argtypes = [P, P, P, P, i64, C.c_float, C.c_float]
         L.mibh_leapfrog.argtypes = [P, P, P, P, i64, C.c_float, C.c_float, C.c_int, C.c_int, P, P, P, C.c_int,
                                     C.POINTER(C.c_int)]
@@ -253,6 +257,35 @@ class Context:
         self._out = (acc, pot)
         return acc, pot
 
+    def refit(self, pos, mass):
+        """New positions and masses for the particles of the last build (same n, input order):
+        the tree is kept, the particles are moved into its order again; call compute_multipoles next."""
+        import torch
+        _require(pos, torch.float32, (3,), self.device, "pos")
+        _require(mass, torch.float32, (), self.device, "mass")
+        if pos.shape[0] != self.n or mass.shape[0] != self.n:
+            raise ValueError("refit needs the particle count of the last build")
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_refit(self.handle, pos.data_ptr(), mass.data_ptr()))
+        self._keep = (pos, mass)
+
+    def compute_forces_active(self, theta: float, active, acc, pot):
+        """Forces for the groups holding a particle with active[i] != 0 (uint8 or bool [n] device
+        tensor); acc/pot entries of the other groups' particles are left as they are."""
+        import torch
+        if active.dtype == torch.bool:
+            active = active.view(torch.uint8)
+        _require(active, torch.uint8, (), self.device, "active")
+        _require(acc, torch.float32, (3,), self.device, "acc")
+        _require(pot, torch.float32, (), self.device, "pot")
+        if active.shape[0] != self.n or acc.shape[0] != self.n or pot.shape[0] != self.n:
+            raise ValueError("sizes differ from the tree's particle count")
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_compute_forces_active(self.handle, float(theta), active.data_ptr(), acc.data_ptr(),
+                                                    pot.data_ptr()))
+        self._out = (acc, pot, active)
+        return acc, pot
+
     def forces(self, pos, mass, theta: float, acc=None, pot=None):
         self.build_tree(pos, mass)
         self.compute_multipoles()
@@ -349,7 +382,8 @@ class Context:
                 "multipoles": (torch.float64, (-1, 10)), "delta": (torch.float64, (-1,)),
                 "mac": (torch.float32, (-1, 4)), "quad": (torch.float32, (-1, 8)),
                 "spos": (torch.float32, (-1, 4)), "features": (torch.float32, (-1, MLP_FEATURES)),
-                "predictions": (torch.float32, (-1,)), "queue": (torch.int32, (-1,))}[what]
+                "predictions": (torch.float32, (-1,)), "queue": (torch.int32, (-1,)),
+                "lside": (torch.float64, (-1,))}[what]
         return buf.view(view[0]).reshape(view[1])
 
 

@@ -1,0 +1,128 @@
+"""Refit and active-group walks on the GPU against the oracle.
+
+* Fresh builds: l' (MIBH_EXPORT_LSIDE) equals the oracle's bit for bit.
+* Refit after a drift: moved particles, float64 moments, delta, l', MAC data
+  and interaction counts bit-exact; forces within 1e-5 at p99.
+* Active walk: only the groups holding an active particle are visited; their
+  counts are bit-exact and their particles' forces within 1e-5 at p99 of the
+  oracle's walk of the same groups; every other particle's outputs are
+  untouched.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import TOL_P99, assert_multipoles_equal, gpu_context, p99, rel_err
+from paper_1204_2280_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _drift(pos, vel, dt):
+    return (pos.astype(np.float64) + dt * vel.astype(np.float64)).astype(np.float32)
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def test_lside_of_fresh_build(orc):
+    pos, _, mass = W.plummer(20000, 41)
+    ctx = gpu_context(len(mass))
+    ctx.forces(_t(pos), _t(mass), 0.75)
+    ctx.sync()
+    T = orc.Tree(pos, mass)
+    np.testing.assert_array_equal(ctx.export("lside").cpu().numpy(), T.multipoles()["lside"])
+
+
+@pytest.mark.parametrize("dt", [0.0625, 0.5])
+def test_refit_matches_oracle(orc, dt):
+    import torch
+    pos, vel, mass = W.plummer(30000, 42)
+    new = _drift(pos, vel, dt)
+    print(f"[gpu] refit n={len(mass)} dt={dt}", flush=True)
+    ctx = gpu_context(len(mass))
+    ctx.build_tree(_t(pos), _t(mass))
+    P1, M1 = _t(new), _t(mass)
+    ctx.refit(P1, M1)
+    ctx.compute_multipoles()
+    acc, pot = ctx.compute_forces(0.75)
+    ctx.sync()
+    T = orc.Tree(pos, mass)
+    T.refit(new, mass)
+    T.walk(0.75)
+    spos = ctx.export("spos").cpu().numpy()
+    np.testing.assert_array_equal(spos[:, :3], new[T.perm])
+    np.testing.assert_array_equal(spos[:, 3], mass[T.perm])
+    om = T.multipoles()
+    g = {"multipoles": ctx.export("multipoles").cpu().numpy(), "delta": ctx.export("delta").cpu().numpy(),
+         "mac": ctx.export("mac").cpu().numpy()}
+    assert_multipoles_equal(g, T, 0.75)
+    lside = ctx.export("lside").cpu().numpy()
+    np.testing.assert_array_equal(lside, om["lside"])
+    grown = int(np.sum(lside > np.ldexp(1.0, T.k - T.cells()["level"])))
+    print(f"[gpu] refit: {grown} of {T.ncells} cells grew", flush=True)
+    assert grown > 0
+    mac = ctx.export("mac").cpu().numpy()
+    omac = T.mac_prep(0.75)
+    np.testing.assert_array_equal(mac[:, :3], omac["com32"])
+    np.testing.assert_array_equal(mac[:, 3], omac["r2open"])
+    counts = ctx.export("counts").cpu().numpy().view(np.uint32).astype(np.int64)
+    npc, npp = T.counts()
+    np.testing.assert_array_equal(counts[:, 0], npc)
+    np.testing.assert_array_equal(counts[:, 1], npp)
+    a, p = T.forces()
+    assert p99(rel_err(acc.cpu().numpy(), a)) <= TOL_P99
+    assert p99(rel_err(pot.cpu().numpy(), p)) <= TOL_P99
+
+
+def test_refit_to_same_positions_equals_build():
+    pos, _, mass = W.plummer(20000, 43)
+    P, M = _t(pos), _t(mass)
+    a = gpu_context(len(mass))
+    acc0, pot0 = a.forces(P, M, 0.75)
+    a.sync()
+    acc0, pot0 = acc0.clone(), pot0.clone()
+    a.refit(P, M)
+    a.compute_multipoles()
+    acc1, pot1 = a.compute_forces(0.75)
+    a.sync()
+    assert bool((acc0 == acc1).all()) and bool((pot0 == pot1).all())
+
+
+def test_active_walk_matches_oracle(orc):
+    import torch
+    pos, _, mass = W.plummer(40000, 44)
+    n = len(mass)
+    rng = np.random.default_rng(3)
+    active = (rng.random(n) < 0.05).astype(np.uint8)
+    ctx = gpu_context(n)
+    P, M = _t(pos), _t(mass)
+    ctx.build_tree(P, M)
+    ctx.compute_multipoles()
+    acc = torch.full((n, 3), 7.0, device="cuda")
+    pot = torch.full((n,), 7.0, device="cuda")
+    ctx.compute_forces_active(0.75, _t(active), acc, pot)
+    ctx.sync()
+    T = orc.Tree(pos, mass)
+    g = T.groups()
+    sorted_active = active[T.perm]
+    gsel = np.array([k for k in range(T.ngroups)
+                     if sorted_active[g["first"][k]:g["first"][k] + g["count"][k]].any()], np.int64)
+    print(f"[gpu] active walk: {active.sum()} active particles in {len(gsel)} of {T.ngroups} groups", flush=True)
+    T.walk_groups(0.75, gsel)
+    visited = np.zeros(n, bool)
+    for k in gsel:
+        visited[T.perm[g["first"][k]:g["first"][k] + g["count"][k]]] = True
+    a, p = T.forces()
+    ga, gp = acc.cpu().numpy(), pot.cpu().numpy()
+    assert p99(rel_err(ga[visited], a[visited])) <= TOL_P99
+    assert p99(rel_err(gp[visited], p[visited])) <= TOL_P99
+    assert np.all(ga[~visited] == 7.0) and np.all(gp[~visited] == 7.0)
+    counts = ctx.export("counts").cpu().numpy().view(np.uint32).astype(np.int64)
+    npc, npp = T.counts()
+    np.testing.assert_array_equal(counts[gsel, 0], npc[gsel])
+    np.testing.assert_array_equal(counts[gsel, 1], npp[gsel])
+    q = ctx.export("queue").cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(q[:len(gsel)], gsel)
+    np.testing.assert_array_equal(np.sort(q), np.arange(T.ngroups))

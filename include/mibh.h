@@ -209,6 +209,44 @@ mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float
                           float theta, float dt, int nsteps, int log_every, float *d_acc, float *d_pot,
                           double *h_log, int log_cap, int *nlog);
 
+/* Block time steps (the paper's Results and Discussion sections: the walk
+ * visits only the particles that are due, the tree is refitted between
+ * rebuilds and rebuilt when the walk slows down).  The paper names no scheme;
+ * this one is hierarchical kick-drift-kick:
+ *   - particle i steps with dt_max / 2^r_i, r_i in 0..max_level, the smallest
+ *     r with dt_max / 2^r <= eta sqrt(eps / |a_i|) (r = 0 for a = 0);
+ *   - a clock ticks in dt_max / 2^max_level; every particle drifts every
+ *     tick; at tick s the particles with 2^(max_level - r_i) dividing s are
+ *     due: the tree is refitted (mibh_refit) or rebuilt, the groups holding a
+ *     due particle are walked (mibh_compute_forces_active), and each due
+ *     particle gets its closing half kick, a new level (a larger step only
+ *     where the tick is a boundary of it) and its opening half kick;
+ *   - after each walk the walked groups' work count * (1 + n_pc + n_pp) is
+ *     summed against the same groups' work at their first walk after the last
+ *     build; when the ratio exceeds 1 + rebuild_tol the next tick rebuilds
+ *     (rebuild_tol < 0: every tick rebuilds; with max_level 0 this is the
+ *     shared-step mibh_leapfrog).
+ * mibh_block_run starts from synchronised velocities, runs nbig steps of
+ * dt_max and returns synchronised velocities, d_acc/d_pot at the final
+ * positions and, when d_level is not NULL, the levels of the last step (uint8
+ * [n]).  h_log (host, >= nbig + 1 rows, NULL: none) gets (t, T, W) in float64
+ * at every multiple of dt_max.  Synchronises once per tick.  Errors: EINVAL
+ * (parameters, pointers, n), as mibh_forces. */
+typedef struct {
+    float dt_max;       /* largest step */
+    int32_t max_level;  /* 0..20: steps dt_max / 2^r, r <= max_level */
+    float eta, eps;     /* step criterion dt = eta * sqrt(eps / |a|) */
+    float rebuild_tol;  /* rebuild when the walked groups' work grows beyond (1 + rebuild_tol) */
+} mibh_block_params;
+typedef struct {
+    int64_t substeps, rebuilds;     /* ticks run; rebuilds after the first build */
+    int64_t active_updates;         /* sum over ticks of the particles due */
+    int64_t groups_walked;          /* sum over ticks of the groups walked */
+} mibh_block_stats;
+mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_mass, int64_t n,
+                           float theta, const mibh_block_params *bp, int nbig, float *d_acc, float *d_pot,
+                           uint8_t *d_level, mibh_block_stats *stats, double *h_log, int log_cap, int *nlog);
+
 /* Device-to-device copy of an internal array of the current tree (for tests
  * and tools).  bytes must be at least the size reported by mibh_export_bytes.
  *   MIBH_EXPORT_KEYS    uint64 [n]        sorted Morton keys

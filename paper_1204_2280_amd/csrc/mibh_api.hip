@@ -37,7 +37,7 @@ struct mibh_ctx {
     int64_t n;
     const float *pos, *mass;
     float *acc, *pot;
-    double *h_energy;  // pinned 2 doubles for mibh_energy
+    double *h_energy;  // pinned 4 words: mibh_energy's two sums, or the block driver's counters
     double *d_energy;  // 2 doubles in the workspace
     // stage events: MIBH_NSTAGES + 1 per profiled step
     hipEvent_t *events;
@@ -139,6 +139,10 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.wstack = (uint32_t *)take(4 * (size_t)STACK_CAP * waves);
     t.feat = (float *)take(4 * (size_t)MLP_IN * n);
     t.pred = (float *)take(4 * n);
+    t.level = (uint8_t *)take(4 * ((n + 3) / 4));
+    t.active = (uint8_t *)take(n);
+    t.gref = (uint32_t *)take(4 * n);
+    t.bsum = (unsigned long long *)take(8 * 4);
     t.qorder = (uint32_t *)take(4 * n);
     t.ohist = (uint32_t *)take(4 * ORDER_BUCKETS * ORDER_BLOCKS);
     t.epart = (double *)take(8 * 2 * ENERGY_BLOCKS + 16);
@@ -237,7 +241,7 @@ mibh_status mibh_create(const mibh_params *pp, int64_t n_max, void *d_workspace,
     }
     layout(n_max, p, (char *)d_workspace, &c->b);
     c->d_energy = c->b.epart + 2 * ENERGY_BLOCKS;
-    e = hipHostMalloc((void **)&c->h_energy, 2 * sizeof(double), hipHostMallocDefault);
+    e = hipHostMalloc((void **)&c->h_energy, 4 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "hipHostMalloc");
@@ -450,6 +454,102 @@ mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float
         HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, (unsigned)n, half, 0.0f, ctx->stream), "kick");
         if (log_every > 0 && s % log_every == 0 && (st = record(s))) return st;
     }
+    return MIBH_OK;
+}
+
+mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_mass, int64_t n,
+                           float theta, const mibh_block_params *bp, int nbig, float *d_acc, float *d_pot,
+                           uint8_t *d_level, mibh_block_stats *stats, double *h_log, int log_cap, int *nlog) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!bp || !d_pos || !d_vel || !d_mass || !d_acc || !d_pot) return fail(MIBH_EINVAL, "null pointer");
+    const int R = bp->max_level;
+    if (R < 0 || R > 20) return fail(MIBH_EINVAL, "max_level %d outside [0, 20]", R);
+    if (!(bp->dt_max > 0.0f) || !isfinite(bp->dt_max)) return fail(MIBH_EINVAL, "dt_max must be finite and > 0");
+    if (!(bp->eta > 0.0f) || !(bp->eps > 0.0f) || !isfinite(bp->eta) || !isfinite(bp->eps))
+        return fail(MIBH_EINVAL, "eta and eps must be finite and > 0");
+    if (!isfinite(bp->rebuild_tol)) return fail(MIBH_EINVAL, "rebuild_tol must be finite");
+    if (nbig < 0) return fail(MIBH_EINVAL, "nbig must be >= 0");
+    if (h_log && log_cap < nbig + 1) return fail(MIBH_EINVAL, "energy log needs %d rows", nbig + 1);
+    if (n < 1 || n > ctx->n_max)
+        return fail(MIBH_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)ctx->n_max);
+    const unsigned un = (unsigned)n, nsub = 1u << R;
+    const float dt_min = ldexpf(bp->dt_max, -R);
+    const double eta = bp->eta, eps = bp->eps;
+    hipStream_t s = ctx->stream;
+    mibh_block_stats stt = {0, 0, 0, 0};
+    int k = 0;
+    if (nlog) *nlog = 0;
+    unsigned long long *h_cnt = reinterpret_cast<unsigned long long *>(ctx->h_energy);
+    auto record = [&](int big) -> mibh_status {
+        double T = 0.0, W = 0.0;
+        mibh_status s2 = mibh_energy(ctx, d_vel, &T, &W);
+        if (s2) return s2;
+        h_log[3 * k] = (double)big * (double)bp->dt_max;
+        h_log[3 * k + 1] = T;
+        h_log[3 * k + 2] = W;
+        k++;
+        if (nlog) *nlog = k;
+        return MIBH_OK;
+    };
+    auto reset_refs = [&]() -> hipError_t { return launch_fill_u32(ctx->b.gref, un, 0u, s); };
+
+    // forces at the start, every particle
+    if ((st = mibh_forces(ctx, d_pos, d_mass, n, theta, d_acc, d_pot))) return st;
+    HIP_TRY(reset_refs(), "gref");
+    if (h_log && (st = record(0))) return st;
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->b.level), (un + 3u) / 4u, 0u, s), "levels");
+    HIP_TRY(launch_block_kick(d_vel, d_acc, ctx->b.level, un, 0u, R, bp->dt_max,
+                              nbig > 0 ? BLOCK_LEVEL | BLOCK_OPEN : BLOCK_LEVEL, eta, eps, s),
+            "kick");
+    bool rebuild = bp->rebuild_tol < 0.0f;  // negative: every tick rebuilds, the first one too
+    for (int big = 0; big < nbig; big++) {
+        for (unsigned tick = 1; tick <= nsub; tick++) {
+            HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, un, 0.0f, dt_min, s), "drift");
+            HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->b.bsum), 8u, 0u, s), "counters");
+            HIP_TRY(launch_block_active(ctx->b.level, un, tick, R, ctx->b.active, ctx->b.bsum + 2, s), "due");
+            if (rebuild) {
+                if ((st = mibh_build_tree(ctx, d_pos, d_mass, n))) return st;
+                HIP_TRY(reset_refs(), "gref");
+                stt.rebuilds++;
+                rebuild = false;
+            } else if ((st = mibh_refit(ctx, d_pos, d_mass))) {
+                return st;
+            }
+            if ((st = mibh_compute_multipoles(ctx))) return st;
+            if ((st = forces_impl(ctx, theta, ctx->b.active, d_acc, d_pot))) return st;
+            HIP_TRY(launch_rebuild_check(ctx->b, ctx->b.ohist + ORDER_BLOCKS, ctx->b.bsum, s), "rebuild check");
+            HIP_TRY(hipMemcpyAsync(h_cnt, ctx->b.bsum, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+                    "hipMemcpyAsync(counters)");
+            HIP_TRY(hipMemcpyAsync(&h_cnt[3], ctx->b.ohist + ORDER_BLOCKS, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   s),
+                    "hipMemcpyAsync(groups)");
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+            const unsigned long long work_now = h_cnt[0], work_ref = h_cnt[1];
+            stt.active_updates += (int64_t)h_cnt[2];
+            stt.groups_walked += (int64_t)(uint32_t)h_cnt[3];
+            stt.substeps++;
+            rebuild = bp->rebuild_tol < 0.0f ||
+                      (work_ref > 0 && (double)work_now > (1.0 + (double)bp->rebuild_tol) * (double)work_ref);
+            if (tick == nsub) {  // every particle is due: synchronised velocities in between the kicks
+                HIP_TRY(launch_block_kick(d_vel, d_acc, ctx->b.level, un, tick, R, bp->dt_max, BLOCK_CLOSE, eta, eps,
+                                          s),
+                        "kick");
+                if (h_log && (st = record(big + 1))) return st;
+                if (big + 1 < nbig)
+                    HIP_TRY(launch_block_kick(d_vel, d_acc, ctx->b.level, un, tick, R, bp->dt_max,
+                                              BLOCK_LEVEL | BLOCK_OPEN, eta, eps, s),
+                            "kick");
+            } else {
+                HIP_TRY(launch_block_kick(d_vel, d_acc, ctx->b.level, un, tick, R, bp->dt_max,
+                                          BLOCK_CLOSE | BLOCK_LEVEL | BLOCK_OPEN, eta, eps, s),
+                        "kick");
+            }
+        }
+    }
+    if (d_level) HIP_TRY(hipMemcpyAsync(d_level, ctx->b.level, un, hipMemcpyDeviceToDevice, s), "levels out");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (stats) *stats = stt;
     return MIBH_OK;
 }
 

@@ -99,6 +99,10 @@ struct Buffers {
     uint32_t *wstack;       // per walk wave: STACK_CAP (spill of the LDS stack)
     float *feat;            // work estimator: group features [n][8]
     float *pred;            // work estimator: predicted log2(1 + n_pc + n_pp) per group
+    uint8_t *level;         // block time steps: level of every particle (input order)
+    uint8_t *active;        // block time steps: particle due at the current tick
+    uint32_t *gref;         // block time steps: work of a group at its first walk after a build (0: none)
+    unsigned long long *bsum;  // block time steps: [0] work now, [1] reference work, [2] due particles
     uint32_t *qorder;       // walk queue: groups in processing order (work-ordered modes)
     uint32_t *ohist;        // [ORDER_BUCKETS][ORDER_BLOCKS] bucket counts of the queue order
     double *epart;          // energy partials [ENERGY_BLOCKS][2]
@@ -151,6 +155,14 @@ hipError_t launch_pack(const Buffers &b, const float *pos, const float *mass, un
 // v <- v + dt_kick a, then (dt_drift != 0) x <- x + dt_drift v, for n particles
 hipError_t launch_kick_drift(float *pos, float *vel, const float *acc, unsigned n, float dt_kick, float dt_drift,
                              hipStream_t s);
+// block time steps
+enum : int { BLOCK_CLOSE = 1, BLOCK_LEVEL = 2, BLOCK_OPEN = 4 };
+hipError_t launch_block_active(const uint8_t *level, unsigned n, unsigned tick, int R, uint8_t *active,
+                               unsigned long long *nactive, hipStream_t s);
+hipError_t launch_block_kick(float *vel, const float *acc, uint8_t *level, unsigned n, unsigned tick, int R,
+                             float dt_max, int flags, double eta, double eps, hipStream_t s);
+hipError_t launch_rebuild_check(const Buffers &b, const uint32_t *qlen, unsigned long long *sums, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, unsigned n, uint32_t v, hipStream_t s);
 hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
                          unsigned n, double *d_out2, hipStream_t s);
 

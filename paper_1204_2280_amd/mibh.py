@@ -24,6 +24,16 @@ EXPORTS = {
     "mac": 7, "quad": 8, "spos": 9, "features": 10, "predictions": 11, "queue": 12, "lside": 13,
 }
 ORDER_MORTON, ORDER_ESTIMATOR, ORDER_EXACT = 0, 1, 2
+
+
+class BlockParams(C.Structure):
+    _fields_ = [("dt_max", C.c_float), ("max_level", C.c_int32), ("eta", C.c_float), ("eps", C.c_float),
+                ("rebuild_tol", C.c_float)]
+
+
+class BlockStats(C.Structure):
+    _fields_ = [("substeps", C.c_int64), ("rebuilds", C.c_int64), ("active_updates", C.c_int64),
+                ("groups_walked", C.c_int64)]
 MLP_FEATURES, MLP_PARAMS = 8, 4801
 STAGES = ("sorting", "moving", "tree_construction", "multipoles", "mac_prep", "walk")
 STATUS = {0: "MIBH_OK", -1: "MIBH_EINVAL", -2: "MIBH_ENOMEM", -3: "MIBH_EHIP", -4: "MIBH_ESTATE",
@@ -91,6 +101,9 @@ def lib():
         L.mibh_leapfrog.argtypes = [P, P, P, P, i64, C.c_float, C.c_float, C.c_int, C.c_int, P, P, P, C.c_int,
                                     C.POINTER(C.c_int)]
         L.mibh_kick_drift.restype = st
+        L.mibh_block_run.argtypes = [P, P, P, P, i64, C.c_float, C.POINTER(BlockParams), C.c_int, P, P, P,
+                                     C.POINTER(BlockStats), P, C.c_int, C.POINTER(C.c_int)]
+        L.mibh_block_run.restype = st
         L.mibh_leapfrog.restype = st
         L.mibh_group_features.argtypes = [P, C.c_float, P]
         L.mibh_set_queue_order.argtypes = [P, C.c_int, P]
@@ -330,6 +343,35 @@ class Context:
         self._keep = (pos, mass)
         self._out = (acc, pot)
         return acc, pot, log[:nlog.value]
+
+    def block_run(self, pos, vel, mass, theta: float, dt_max: float, max_level: int, eta: float, eps: float,
+                  nbig: int, rebuild_tol: float = 0.25, log: bool = True, acc=None, pot=None, levels=None):
+        """nbig block-time-step steps of dt_max (pos and vel updated in place, synchronised on return).
+        Returns (acc, pot, levels uint8 [n], stats dict, energy log rows (t, T, W) per dt_max)."""
+        import numpy as np
+        import torch
+        n = int(mass.shape[0])
+        _require(pos, torch.float32, (3,), self.device, "pos")
+        _require(vel, torch.float32, (3,), self.device, "vel")
+        _require(mass, torch.float32, (), self.device, "mass")
+        if pos.shape[0] != n or vel.shape[0] != n:
+            raise ValueError("pos, vel and mass sizes differ")
+        acc = torch.empty((n, 3), dtype=torch.float32, device=self.device) if acc is None else acc
+        pot = torch.empty((n,), dtype=torch.float32, device=self.device) if pot is None else pot
+        levels = torch.empty((n,), dtype=torch.uint8, device=self.device) if levels is None else levels
+        bp = BlockParams(float(dt_max), int(max_level), float(eta), float(eps), float(rebuild_tol))
+        stats = BlockStats()
+        rows = np.zeros((int(nbig) + 1, 3), dtype=np.float64)
+        nlog = C.c_int(0)
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_block_run(self.handle, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), n,
+                                        float(theta), C.byref(bp), int(nbig), acc.data_ptr(), pot.data_ptr(),
+                                        levels.data_ptr(), C.byref(stats),
+                                        rows.ctypes.data if log else None, rows.shape[0], C.byref(nlog)))
+        self.n = n
+        self._keep = (pos, mass)
+        self._out = (acc, pot)
+        return acc, pot, levels, {f: getattr(stats, f) for f, _ in BlockStats._fields_}, rows[:nlog.value]
 
     def sync(self):
         _check(lib().mibh_sync(self.handle))

@@ -272,6 +272,49 @@ def bench_variant_leapfrog(n, seed, theta, steps):
             "rel_energy_drift": float(abs(E[-1] - E[0]) / abs(E[0]))}
 
 
+def bench_variant_block_steps(n, seed, theta, shared_ms):
+    """Block time steps on the same Plummer sphere with velocities (softening
+    eps = 0.01): steps of dt_max = 1/16 in 16 ticks (levels 0..4, criterion
+    dt = 0.1 sqrt(0.1 / |a|)), refits between work-triggered rebuilds
+    (tolerance 0.25).  A run starts with a force evaluation of every particle;
+    the steady time per dt_max is (t(3 steps) - t(1 step)) / 2.  It is
+    compared with 16 shared steps of the smallest step dt_max/16 (every
+    particle updated every tick) at the leapfrog driver's time per step."""
+    import torch
+    from paper_1204_2280_amd import mibh, workloads
+    pos, vel, mass = workloads.plummer(n, seed)
+    dev = torch.device("cuda", 0)
+    P, V, M = (torch.from_numpy(t.copy()).to(dev) for t in (pos, vel, mass))
+    ctx = mibh.Context(n, device=dev, eps2=1e-4)
+    args = (theta, 1.0 / 16, 4, 0.1, 0.1)
+
+    def run(nbig):
+        P.copy_(torch.from_numpy(pos))
+        V.copy_(torch.from_numpy(vel))
+        ctx.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(ctx.stream)
+        _, _, lev, st, _ = ctx.block_run(P, V, M, *args, nbig, log=False)
+        b.record(ctx.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b), lev, st
+
+    run(1)  # warm-up
+    t1, _, st1 = run(1)
+    t3, lev, st3 = run(3)
+    steady = (t3 - t1) / 2
+    hist = torch.bincount(lev.to(torch.int64), minlength=5).cpu().tolist()
+    del ctx
+    upd = (st3["active_updates"] - st1["active_updates"]) / 2
+    out = {"workload": f"plummer_n{n}_seed{seed}_theta{theta:g}_eps2{1e-4:g}_dtmax{1 / 16:g}_levels0-4",
+           "schedule_3_steps": st3, "levels_last_step": hist, "ms_one_step_with_initial_forces": t1,
+           "ms_three_steps": t3, "ms_per_dt_max_steady": steady,
+           "active_fraction": upd / (n * 16), "particle_updates_per_s": upd / (steady * 1e-3)}
+    if shared_ms:
+        out["ms_shared_16_smallest_steps"] = 16 * shared_ms
+        out["speedup_vs_shared_smallest_steps"] = 16 * shared_ms / steady
+    return out
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,6 +439,9 @@ def main():
         result["variant_ensemble"] = bench_variant_ensemble(theta, max(3, args.steps // 4), 1)
         log("[bench] variant: leapfrog driver")
         result["variant_leapfrog"] = bench_variant_leapfrog(n, args.seed, theta, 20)
+        log("[bench] variant: block time steps")
+        result["variant_block_steps"] = bench_variant_block_steps(
+            n, args.seed, theta, result["variant_leapfrog"]["ms_per_step"])
         log("[bench] variant: queue order")
         result["variant_queue_order"] = bench_variant_queue_order(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variants done")

@@ -217,13 +217,15 @@ mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float
  *     r with dt_max / 2^r <= eta sqrt(eps / |a_i|) (r = 0 for a = 0);
  *   - a clock ticks in dt_max / 2^max_level; every particle drifts every
  *     tick; at tick s the particles with 2^(max_level - r_i) dividing s are
- *     due: the tree is refitted (mibh_refit) or rebuilt, the groups holding a
- *     due particle are walked (mibh_compute_forces_active), and each due
+ *     due; if any is, the tree is refitted (mibh_refit) or rebuilt, the
+ *     groups holding a due particle are walked (mibh_compute_forces_active),
+ *     and each due
  *     particle gets its closing half kick, a new level (a larger step only
  *     where the tick is a boundary of it) and its opening half kick;
  *   - after each walk the walked groups' work count * (1 + n_pc + n_pp) is
  *     summed against the same groups' work at their first walk after the last
- *     build; when the ratio exceeds 1 + rebuild_tol the next tick rebuilds
+ *     build (the initial walk of every particle sets all of them); when the
+ *     ratio exceeds 1 + rebuild_tol the next tick with a due particle rebuilds
  *     (rebuild_tol < 0: every tick rebuilds; with max_level 0 this is the
  *     shared-step mibh_leapfrog).
  * mibh_block_run starts from synchronised velocities, runs nbig steps of

@@ -11,13 +11,14 @@ the walk slows down; it names no scheme.  The reading taken, step by step:
   dt_max / 2^r <= eta sqrt(eps / |a_i|) (r = 0 for a = 0), taken in float64
   as the smallest r with 16^r >= dt_max^4 |a|^2 / (eta^4 eps^2);
 * a clock ticks in dt_max / 2^R; every particle drifts every tick; at tick s
-  the particles whose 2^(R - r_i) divides s are due: the tree is refitted (or
-  rebuilt), the groups holding a due particle are walked, and each due
+  the particles whose 2^(R - r_i) divides s are due; if any is, the tree is
+  refitted (or rebuilt), the groups holding a due particle are walked, and each due
   particle gets its closing half kick (old level), a new level (at least
   R - (trailing zeros of s), so that its next step starts on its own grid)
   and its opening half kick;
 * after each walk, the walked groups' work count * (1 + n_pc + n_pp) is
-  summed against their work at their first walk after the last build; when
+  summed against their work at their first walk after the last build (the
+  initial walk sets every group's); when
   it exceeds (1 + tol) times that, the next tick rebuilds (tol < 0: every
   tick rebuilds).
 
@@ -76,7 +77,8 @@ def block_run(pos, vel, mass, theta, dt_max, R, eta, eps, nbig, tol=0.25, eps2=0
     T = Tree(x, m, ncrit, gcap)
     T.walk(theta, eps2, G, nthreads=nthreads)
     a, p = (t.copy() for t in T.forces())
-    gref = np.zeros(T.ngroups, np.int64)
+    npc, npp = T.counts()
+    gref = T.groups()["count"] * (1 + npc + npp)  # the first walk sets every group's reference work
     stats = {"substeps": 0, "rebuilds": 0, "active_updates": 0, "groups_walked": 0}
     log = [(0.0, *energy(m, p, v))]
     lev = level_of(a, dt_max, eta, eps, R)
@@ -87,6 +89,9 @@ def block_run(pos, vel, mass, theta, dt_max, R, eta, eps, nbig, tol=0.25, eps2=0
         for tick in range(1, nsub + 1):
             x = (x.astype(np.float64) + dt_min * v.astype(np.float64)).astype(np.float32)
             due = (tick % (1 << (R - lev))) == 0
+            stats["substeps"] += 1
+            if not due.any():  # nobody is due: the particles only drift (a pending rebuild waits)
+                continue
             if rebuild:
                 T = Tree(x, m, ncrit, gcap)
                 gref = np.zeros(T.ngroups, np.int64)
@@ -111,7 +116,6 @@ def block_run(pos, vel, mass, theta, dt_max, R, eta, eps, nbig, tol=0.25, eps2=0
             known = ref > 0
             work_now, work_ref = int(now[known].sum()), int(ref[known].sum())
             gref[walk[~known]] = now[~known]
-            stats["substeps"] += 1
             stats["active_updates"] += int(due.sum())
             stats["groups_walked"] += len(walk)
             rebuild = tol < 0 or (work_ref > 0 and work_now > (1.0 + tol) * work_ref)

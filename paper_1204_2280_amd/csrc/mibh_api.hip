@@ -140,7 +140,7 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.feat = (float *)take(4 * (size_t)MLP_IN * n);
     t.pred = (float *)take(4 * n);
     t.level = (uint8_t *)take(4 * ((n + 3) / 4));
-    t.active = (uint8_t *)take(n);
+    t.active = (uint8_t *)take(4 * ((n + 3) / 4));
     t.gref = (uint32_t *)take(4 * n);
     t.bsum = (unsigned long long *)take(8 * 4);
     t.qorder = (uint32_t *)take(4 * n);
@@ -494,9 +494,19 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
     };
     auto reset_refs = [&]() -> hipError_t { return launch_fill_u32(ctx->b.gref, un, 0u, s); };
 
-    // forces at the start, every particle
-    if ((st = mibh_forces(ctx, d_pos, d_mass, n, theta, d_acc, d_pot))) return st;
+    // forces at the start, every particle due: the walk also gives every group its reference work
+    auto walk_and_check = [&]() -> mibh_status {
+        mibh_status s2 = forces_impl(ctx, theta, ctx->b.active, d_acc, d_pot);
+        if (s2) return s2;
+        HIP_TRY(launch_rebuild_check(ctx->b, ctx->b.ohist + ORDER_BLOCKS, ctx->b.bsum, s), "rebuild check");
+        return MIBH_OK;
+    };
+    if ((st = mibh_build_tree(ctx, d_pos, d_mass, n))) return st;
+    if ((st = mibh_compute_multipoles(ctx))) return st;
     HIP_TRY(reset_refs(), "gref");
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->b.active), (un + 3u) / 4u, 0x01010101u, s), "due");
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->b.bsum), 8u, 0u, s), "counters");
+    if ((st = walk_and_check())) return st;
     if (h_log && (st = record(0))) return st;
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->b.level), (un + 3u) / 4u, 0u, s), "levels");
     HIP_TRY(launch_block_kick(d_vel, d_acc, ctx->b.level, un, 0u, R, bp->dt_max,
@@ -508,6 +518,12 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
             HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, un, 0.0f, dt_min, s), "drift");
             HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->b.bsum), 8u, 0u, s), "counters");
             HIP_TRY(launch_block_active(ctx->b.level, un, tick, R, ctx->b.active, ctx->b.bsum + 2, s), "due");
+            HIP_TRY(hipMemcpyAsync(&h_cnt[2], ctx->b.bsum + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+                    "hipMemcpyAsync(due)");
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+            stt.substeps++;
+            if (h_cnt[2] == 0) continue;  // nobody is due: the particles only drift (a pending rebuild waits)
+            stt.active_updates += (int64_t)h_cnt[2];
             if (rebuild) {
                 if ((st = mibh_build_tree(ctx, d_pos, d_mass, n))) return st;
                 HIP_TRY(reset_refs(), "gref");
@@ -517,18 +533,15 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
                 return st;
             }
             if ((st = mibh_compute_multipoles(ctx))) return st;
-            if ((st = forces_impl(ctx, theta, ctx->b.active, d_acc, d_pot))) return st;
-            HIP_TRY(launch_rebuild_check(ctx->b, ctx->b.ohist + ORDER_BLOCKS, ctx->b.bsum, s), "rebuild check");
-            HIP_TRY(hipMemcpyAsync(h_cnt, ctx->b.bsum, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+            if ((st = walk_and_check())) return st;
+            HIP_TRY(hipMemcpyAsync(h_cnt, ctx->b.bsum, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
                     "hipMemcpyAsync(counters)");
             HIP_TRY(hipMemcpyAsync(&h_cnt[3], ctx->b.ohist + ORDER_BLOCKS, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                    s),
                     "hipMemcpyAsync(groups)");
             HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
             const unsigned long long work_now = h_cnt[0], work_ref = h_cnt[1];
-            stt.active_updates += (int64_t)h_cnt[2];
             stt.groups_walked += (int64_t)(uint32_t)h_cnt[3];
-            stt.substeps++;
             rebuild = bp->rebuild_tol < 0.0f ||
                       (work_ref > 0 && (double)work_now > (1.0 + (double)bp->rebuild_tol) * (double)work_ref);
             if (tick == nsub) {  // every particle is due: synchronised velocities in between the kicks

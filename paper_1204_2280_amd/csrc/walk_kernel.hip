@@ -165,6 +165,13 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist
 #pragma unroll
         for (int j = 0; j < 64; j++) { v[j] = 0.0f; cv[j] = 0.0f; }
         for (unsigned t0 = 0; t0 < nlist; t0 += 64) {
+            // The particle count of the chunk is taken as new in every tile, so
+            // that its 16 comparisons are made in place (scalar compares) instead
+            // of being kept as 16 lane masks across the loop: 32 scalar registers
+            // more than the wave can hold, spilled to vector-register lanes and
+            // read back in every tile.
+            unsigned cn_t = cn;
+            asm volatile("" : "+s"(cn_t));
             const unsigned k = t0 + ln;
             const bool valid = k < nlist;
             const unsigned e = valid ? list[k] : 0u;
@@ -177,7 +184,7 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist
                 }
 #pragma unroll
                 for (int ii = 0; ii < CHUNK; ii++) {
-                    if ((unsigned)ii < cn) {
+                    if ((unsigned)ii < cn_t) {
                         // R = x - com; r2 = R.R + eps2
                         const float Rx = xi[ii] - m.x, Ry = yi[ii] - m.y, Rz = zi[ii] - m.z;
                         const float r2 = fmaf(Rz, Rz, fmaf(Ry, Ry, fmaf(Rx, Rx, eps2)));
@@ -212,7 +219,7 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist
                 if (!valid) s = make_float4(FAR, FAR, FAR, 0.0f);
 #pragma unroll
                 for (int ii = 0; ii < CHUNK; ii++) {
-                    if ((unsigned)ii < cn) {
+                    if ((unsigned)ii < cn_t) {
                         const float dx = s.x - xi[ii], dy = s.y - yi[ii], dz = s.z - zi[ii];
                         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                         float rinv = __builtin_amdgcn_rsqf(r2 + eps2);

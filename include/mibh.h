@@ -249,6 +249,33 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
                            float theta, const mibh_block_params *bp, int nbig, float *d_acc, float *d_pot,
                            uint8_t *d_level, mibh_block_stats *stats, double *h_log, int log_cap, int *nlog);
 
+/* Neighbour search and SPH density on the current tree (the paper's
+ * Discussion section: the tree serves neighbour search and smoothed particle
+ * hydrodynamics).  Gather form: the neighbours of particle i are the j (i
+ * included) with d2 <= r_i * r_i, d = x_j - x_i, d2 = (dx*dx + dy*dy) + dz*dz,
+ * every operation float32 and rounded.  Needs compute_multipoles (it uses the
+ * cells' particle boxes).  All arrays are device memory in input order.
+ *
+ * mibh_neighbor_count: d_count[i] = number of neighbours within d_radius[i]
+ * (float32 [n], finite, >= 0).
+ *
+ * mibh_neighbor_list: the same counts, d_offset [n+1] their exclusive prefix
+ * sums (d_offset[n] = *total), and, when *total <= capacity, d_index
+ * [capacity] the neighbours' input indices, those of particle i in
+ * d_index[d_offset[i] .. d_offset[i+1]) (order unspecified).  Synchronises
+ * once (to read the total).  Errors: EOVERFLOW when *total > capacity (the
+ * counts, offsets and *total are written), EINVAL, ESTATE.
+ *
+ * mibh_sph_density: d_rho[i] = sum over the neighbours within 2 h_i of
+ * m_j W(|x_j - x_i|, h_i), W the cubic spline of Monaghan & Lattanzio (1985)
+ * (W = (1 - 3/2 q^2 + 3/4 q^3)/(pi h^3) for q = r/h < 1, (2 - q)^3/(4 pi h^3)
+ * for 1 <= q < 2), float32; d_count[i] the number of those neighbours; d_h
+ * float32 [n], > 0. */
+mibh_status mibh_neighbor_count(mibh_ctx *ctx, const float *d_radius, uint32_t *d_count);
+mibh_status mibh_neighbor_list(mibh_ctx *ctx, const float *d_radius, uint32_t *d_count, uint32_t *d_offset,
+                               uint32_t *d_index, int64_t capacity, int64_t *total);
+mibh_status mibh_sph_density(mibh_ctx *ctx, const float *d_h, float *d_rho, uint32_t *d_count);
+
 /* Device-to-device copy of an internal array of the current tree (for tests
  * and tools).  bytes must be at least the size reported by mibh_export_bytes.
  *   MIBH_EXPORT_KEYS    uint64 [n]        sorted Morton keys

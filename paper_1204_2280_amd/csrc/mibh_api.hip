@@ -15,6 +15,8 @@ using namespace mibh;
 
 // queue mode of a walk over the groups holding an active particle (internal)
 constexpr int ORDER_ACTIVE = 3;
+// the neighbour-list offset scan keeps its tile sums in the queue-order counts
+constexpr int SCAN_MAX_TILES = ORDER_BUCKETS * ORDER_BLOCKS;
 
 struct mibh_ctx {
     mibh_params p;
@@ -563,6 +565,56 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
     if (d_level) HIP_TRY(hipMemcpyAsync(d_level, ctx->b.level, un, hipMemcpyDeviceToDevice, s), "levels out");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (stats) *stats = stt;
+    return MIBH_OK;
+}
+
+static mibh_status neighbors_check(mibh_ctx *ctx, const void *radius, const void *out) {
+    mibh_status st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->state < 2) return fail(MIBH_ESTATE, "neighbour search before compute_multipoles");
+    if (!radius || !out) return fail(MIBH_EINVAL, "null pointer");
+    return MIBH_OK;
+}
+
+mibh_status mibh_neighbor_count(mibh_ctx *ctx, const float *d_radius, uint32_t *d_count) {
+    mibh_status st = neighbors_check(ctx, d_radius, d_count);
+    if (st) return st;
+    HIP_TRY(launch_neighbors(ctx->b, 0, d_radius, d_count, nullptr, nullptr, nullptr, (unsigned)ctx->nsys,
+                             ctx->stream),
+            "neighbors");
+    return MIBH_OK;
+}
+
+mibh_status mibh_neighbor_list(mibh_ctx *ctx, const float *d_radius, uint32_t *d_count, uint32_t *d_offset,
+                               uint32_t *d_index, int64_t capacity, int64_t *total) {
+    mibh_status st = neighbors_check(ctx, d_radius, d_count);
+    if (st) return st;
+    if (!d_offset || !total || (capacity > 0 && !d_index)) return fail(MIBH_EINVAL, "null pointer");
+    if ((int64_t)ctx->n > (int64_t)SCAN_MAX_TILES * 1024)
+        return fail(MIBH_EINVAL, "too many particles for the offset scan");
+    HIP_TRY(launch_neighbors(ctx->b, 0, d_radius, d_count, nullptr, nullptr, nullptr, (unsigned)ctx->nsys,
+                             ctx->stream),
+            "neighbors");
+    HIP_TRY(launch_scan_u32(d_count, (unsigned)ctx->n, d_offset, ctx->b.ohist, ctx->stream), "scan");
+    uint32_t *h_tot = reinterpret_cast<uint32_t *>(ctx->h_energy);
+    HIP_TRY(hipMemcpyAsync(h_tot, d_offset + ctx->n, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync(total)");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    *total = (int64_t)*h_tot;
+    if (*total > capacity)
+        return fail(MIBH_EOVERFLOW, "%lld neighbours, capacity %lld", (long long)*total, (long long)capacity);
+    HIP_TRY(launch_neighbors(ctx->b, 1, d_radius, d_count, d_offset, d_index, nullptr, (unsigned)ctx->nsys,
+                             ctx->stream),
+            "neighbors");
+    return MIBH_OK;
+}
+
+mibh_status mibh_sph_density(mibh_ctx *ctx, const float *d_h, float *d_rho, uint32_t *d_count) {
+    mibh_status st = neighbors_check(ctx, d_h, d_rho);
+    if (st) return st;
+    if (!d_count) return fail(MIBH_EINVAL, "null count pointer");
+    HIP_TRY(launch_neighbors(ctx->b, 2, d_h, d_count, nullptr, nullptr, d_rho, (unsigned)ctx->nsys, ctx->stream),
+            "density");
     return MIBH_OK;
 }
 

@@ -163,6 +163,11 @@ hipError_t launch_block_kick(float *vel, const float *acc, uint8_t *level, unsig
                              float dt_max, int flags, double eta, double eps, hipStream_t s);
 hipError_t launch_rebuild_check(const Buffers &b, const uint32_t *qlen, unsigned long long *sums, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, unsigned n, uint32_t v, hipStream_t s);
+// neighbour search (mode 0 counts, 1 lists, 2 SPH density); needs the cell boxes of compute_multipoles
+hipError_t launch_neighbors(const Buffers &b, int mode, const float *radius, uint32_t *count, const uint32_t *offset,
+                            uint32_t *index, float *rho, unsigned nsys, hipStream_t s);
+// exclusive scan of n counts into out[0..n], out[n] = total; tmp holds (n + 1023) / 1024 words
+hipError_t launch_scan_u32(const uint32_t *in, unsigned n, uint32_t *out, uint32_t *tmp, hipStream_t s);
 hipError_t launch_energy(const Buffers &b, const float *mass, const float *pot, const float *vel,
                          unsigned n, double *d_out2, hipStream_t s);
 

@@ -104,6 +104,11 @@ def lib():
         L.mibh_block_run.argtypes = [P, P, P, P, i64, C.c_float, C.POINTER(BlockParams), C.c_int, P, P, P,
                                      C.POINTER(BlockStats), P, C.c_int, C.POINTER(C.c_int)]
         L.mibh_block_run.restype = st
+        L.mibh_neighbor_count.argtypes = [P, P, P]
+        L.mibh_neighbor_list.argtypes = [P, P, P, P, P, i64, C.POINTER(i64)]
+        L.mibh_sph_density.argtypes = [P, P, P, P]
+        for f in ("mibh_neighbor_count", "mibh_neighbor_list", "mibh_sph_density"):
+            getattr(L, f).restype = st
         L.mibh_leapfrog.restype = st
         L.mibh_group_features.argtypes = [P, C.c_float, P]
         L.mibh_set_queue_order.argtypes = [P, C.c_int, P]
@@ -372,6 +377,53 @@ class Context:
         self._keep = (pos, mass)
         self._out = (acc, pot)
         return acc, pot, levels, {f: getattr(stats, f) for f, _ in BlockStats._fields_}, rows[:nlog.value]
+
+    def _radius(self, r, name):
+        import torch
+        _require(r, torch.float32, (), self.device, name)
+        if r.shape[0] != self.n:
+            raise ValueError(f"{name} needs one value per particle of the tree")
+
+    def neighbor_count(self, radius):
+        """Neighbours of each particle within radius[i] (itself included), uint32 [n] as int32 tensor."""
+        import torch
+        self._radius(radius, "radius")
+        count = torch.empty((self.n,), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_neighbor_count(self.handle, radius.data_ptr(), count.data_ptr()))
+        return count
+
+    def neighbor_list(self, radius, capacity=None):
+        """(counts, offsets [n+1], indices): the neighbours of particle i are
+        indices[offsets[i]:offsets[i+1]] (input indices, unordered).  With capacity None the
+        list is sized from the counts (two passes)."""
+        import torch
+        self._radius(radius, "radius")
+        count = torch.empty((self.n,), dtype=torch.int32, device=self.device)
+        offset = torch.empty((self.n + 1,), dtype=torch.int32, device=self.device)
+        total = C.c_int64(0)
+        if capacity is None:
+            with torch.cuda.device(self.device):
+                st = lib().mibh_neighbor_list(self.handle, radius.data_ptr(), count.data_ptr(), offset.data_ptr(),
+                                              None, 0, C.byref(total))
+            if st not in (0, -5):
+                _check(st)
+            capacity = total.value
+        index = torch.empty((max(int(capacity), 1),), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_neighbor_list(self.handle, radius.data_ptr(), count.data_ptr(), offset.data_ptr(),
+                                            index.data_ptr(), int(capacity), C.byref(total)))
+        return count, offset, index[:total.value]
+
+    def sph_density(self, h):
+        """(rho float32 [n], neighbour counts within 2 h) with the cubic-spline kernel."""
+        import torch
+        self._radius(h, "h")
+        rho = torch.empty((self.n,), dtype=torch.float32, device=self.device)
+        count = torch.empty((self.n,), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().mibh_sph_density(self.handle, h.data_ptr(), rho.data_ptr(), count.data_ptr()))
+        return rho, count
 
     def sync(self):
         _check(lib().mibh_sync(self.handle))

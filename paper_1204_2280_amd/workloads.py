@@ -184,3 +184,17 @@ def uniform_cube(n: int, seed: int, side: float = 1.0):
     pos = np.stack([uniform(seed, s, 0, n) for s in (S_RADIUS, S_COST, S_PHI)], axis=1) * side
     return (np.ascontiguousarray(pos, dtype=np.float32),
             np.full(n, 1.0 / max(n, 1), dtype=np.float32))
+
+
+def plummer_smoothing_lengths(pos, n_ngb: int = 64):
+    """Smoothing lengths for SPH inputs on a Henon-unit Plummer sphere of
+    len(pos) equal masses (total mass 1): h such that a sphere of radius 2h
+    around the particle holds n_ngb particles on average under the analytic
+    density rho(r) = 3/(4 pi a^3) (1 + r^2/a^2)^(-5/2), a = 3 pi/16 (the
+    sphere is centred on the origin).  float32 [n]."""
+    p = np.asarray(pos, np.float64)
+    a = 3.0 * np.pi / 16.0
+    r2 = np.sum(p * p, axis=1)
+    rho = 3.0 / (4.0 * np.pi * a ** 3) * (1.0 + r2 / (a * a)) ** -2.5
+    num = len(p) * rho
+    return (0.5 * np.cbrt(3.0 * n_ngb / (4.0 * np.pi * num))).astype(np.float32)

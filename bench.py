@@ -315,6 +315,43 @@ def bench_variant_block_steps(n, seed, theta, shared_ms):
         out["speedup_vs_shared_smallest_steps"] = 16 * shared_ms / steady
     return out
 
+def bench_variant_neighbors(pos, mass, steps):
+    """Neighbour search and SPH density on the benchmark sphere (tree of the
+    force step; smoothing lengths from the analytic Plummer density for 64
+    neighbours within 2h): milliseconds of neighbour counting, of CSR
+    neighbour lists (counts, scan, fill) and of the density."""
+    import torch
+    from paper_1204_2280_amd import mibh, workloads
+    n = len(mass)
+    dev = torch.device("cuda", 0)
+    P, M = torch.from_numpy(pos).to(dev), torch.from_numpy(mass).to(dev)
+    h = torch.from_numpy(workloads.plummer_smoothing_lengths(pos, 64)).to(dev)
+    r = 2.0 * h
+    ctx = mibh.Context(n, device=dev)
+    ctx.build_tree(P, M)
+    ctx.compute_multipoles()
+
+    def timed(fn):
+        fn()
+        ctx.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(ctx.stream)
+        for _ in range(steps):
+            out = fn()
+        b.record(ctx.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps, out
+
+    ms_count, cnt = timed(lambda: ctx.neighbor_count(r))
+    total = int(cnt.sum())
+    ms_list, _ = timed(lambda: ctx.neighbor_list(r, capacity=total))
+    ms_rho, _ = timed(lambda: ctx.sph_density(h))
+    del ctx
+    return {"workload": f"plummer_n{n}_ngb64_support2h", "neighbours_per_particle": total / n,
+            "ms_count": ms_count, "ms_list": ms_list, "ms_density": ms_rho,
+            "neighbours_per_s_density": total / (ms_rho * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,6 +479,8 @@ def main():
         log("[bench] variant: block time steps")
         result["variant_block_steps"] = bench_variant_block_steps(
             n, args.seed, theta, result["variant_leapfrog"]["ms_per_step"])
+        log("[bench] variant: neighbour search and SPH density")
+        result["variant_neighbors"] = bench_variant_neighbors(pos, mass, 5)
         log("[bench] variant: queue order")
         result["variant_queue_order"] = bench_variant_queue_order(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variants done")

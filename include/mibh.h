@@ -370,6 +370,17 @@ mibh_status mibh_mlp_gradient(const void *d_w16, const float *d_x, const float *
 mibh_status mibh_mlp_adam(float *d_w32, void *d_w16, const float *d_grad, float *d_m, float *d_v, int step,
                           float lr, float beta1, float beta2, float eps, void *stream);
 
+/* Throughput probe, not part of the method: the rate that plain (non-packed)
+ * float32 fused multiply-adds reach on the running GPU, against which the
+ * walk's algorithmic flop rate is compared.  Launches `blocks` waves of 64
+ * lanes on `stream`; lane l of wave w starts 32 accumulators at
+ * v_j = ((64 w + l) mod 256) / 256 + j / 32 and applies v_j <- fma(a, b, v_j)
+ * `iters` times, then stores them to d_out[(64 w + l) * 32 + j] (caller-owned
+ * device memory of 2048 * blocks floats).  Work: 64 * blocks * iters * 64
+ * flops.  Errors: EINVAL (null d_out, blocks outside [1, 2^20], iters < 0),
+ * EHIP. */
+mibh_status mibh_fma_probe(float *d_out, int32_t blocks, int32_t iters, float a, float b, void *stream);
+
 /* Human-readable status name, and the calling thread's last error message. */
 const char *mibh_status_string(mibh_status s);
 const char *mibh_last_error(void);

@@ -911,6 +911,22 @@ mibh_status mibh_profile_read(mibh_ctx *ctx, float *ms, int max_steps, int *nste
     return MIBH_OK;
 }
 
+}  // extern "C"
+
+namespace mibh {
+// float32 fused multiply-add throughput probe (probe_kernel.hip): out[64 * blocks * 32]
+hipError_t launch_fma_probe(float *out, unsigned blocks, unsigned iters, float a, float b, hipStream_t s);
+}  // namespace mibh
+
+extern "C" {
+
+mibh_status mibh_fma_probe(float *d_out, int32_t blocks, int32_t iters, float a, float b, void *stream) {
+    if (!d_out) return fail(MIBH_EINVAL, "null pointer");
+    if (blocks < 1 || blocks > (1 << 20) || iters < 0) return fail(MIBH_EINVAL, "blocks or iters out of range");
+    HIP_TRY(launch_fma_probe(d_out, (unsigned)blocks, (unsigned)iters, a, b, (hipStream_t)stream), "fma_probe");
+    return MIBH_OK;
+}
+
 const char *mibh_status_string(mibh_status s) {
     switch (s) {
         case MIBH_OK: return "MIBH_OK";

@@ -120,6 +120,8 @@ def lib():
         for f in ("mibh_group_features", "mibh_set_queue_order", "mibh_mlp_forward", "mibh_mlp_gradient",
                   "mibh_mlp_adam"):
             getattr(L, f).restype = st
+        L.mibh_fma_probe.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
+        L.mibh_fma_probe.restype = st
         L.mibh_profile_begin.argtypes = [P, C.c_int]
         L.mibh_profile_read.argtypes = [P, P, C.c_int, C.POINTER(C.c_int)]
         L.mibh_profile_begin.restype = st
@@ -484,6 +486,16 @@ class Context:
 def _stream_ptr(t):
     import torch
     return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def fma_probe(out, blocks: int, iters: int, a: float = 0.5, b: float = 2.0 ** -12):
+    """Launches the float32 fused multiply-add probe on the current stream:
+    `blocks` waves, 32 accumulators per lane, `iters` updates v <- fma(a, b, v);
+    out is float32 [blocks * 64 * 32] on the GPU."""
+    if out.numel() < blocks * 2048:
+        raise ValueError("out holds fewer than 2048 floats per block")
+    _check(lib().mibh_fma_probe(out.data_ptr(), int(blocks), int(iters), float(a), float(b), _stream_ptr(out)))
+    return out
 
 
 def mlp_forward(w16, x, y=None):

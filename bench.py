@@ -101,6 +101,7 @@ def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 2):
         "value": n / t_step,
         "unit": "particles/s",
         "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"float64 oracle: full tree build of all {n} particles ({t_build:.2f} s, one thread) + "
                    f"walk of {sampled} of {ng} groups in {n_ranges} ranges ({t_walk:.2f} s), walk time "
@@ -372,6 +373,60 @@ def bench_variant_neighbors(pos, mass, steps):
             "neighbours_per_s_density": total / (ms_rho * 1e-3)}
 
 
+def paper_sections(stage_ms):
+    """The paper's five sections from the library's stage times."""
+    return {"sorting": stage_ms["sorting"], "moving": stage_ms["moving"],
+            "tree_construction": stage_ms["tree_construction"],
+            "multipoles": stage_ms["multipoles"] + stage_ms["mac_prep"], "tree_traverse": stage_ms["walk"]}
+
+
+def bench_config(pos, mass, theta, steps, warmup):
+    """One force-step configuration: time per step, the paper's sections,
+    interactions per particle and the walk's flop rate."""
+    import numpy as np
+    import torch
+    from paper_1204_2280_amd import mibh
+    n = len(mass)
+    dev = torch.device("cuda", 0)
+    p = torch.from_numpy(pos).to(dev)
+    m = torch.from_numpy(mass).to(dev)
+    ctx = mibh.Context(n, device=dev)
+    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((n,), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        ctx.forces(p, m, theta, acc, pot)
+    ctx.sync()
+    ctx.profile_begin(steps)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(ctx.stream)
+    for _ in range(steps):
+        ctx.forces(p, m, theta, acc, pot)
+    b.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    stages = ctx.profile_read()
+    ctx.sync()
+    st = ctx.stats()
+    stage_ms = {k: float(np.mean([x[k] for x in stages])) for k in mibh.STAGES}
+    flops = F_PC * st["sum_pc"] + F_PP * st["sum_pp"]
+    del ctx
+    return {"n": n, "theta": theta, "ms_per_step": ms, "particles_per_s": n / (ms * 1e-3),
+            "paper_sections_ms": paper_sections(stage_ms),
+            "interactions_per_particle": {"pc": st["sum_pc"] / n, "pp": st["sum_pp"] / n},
+            "walk_tflops": flops / (stage_ms["walk"] * 1e-3) / 1e12}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,11 +492,8 @@ def main():
     inter = st["sum_pc"] + st["sum_pp"]
     flops = F_PC * st["sum_pc"] + F_PP * st["sum_pp"]
     achieved = flops / (walk_ms * 1e-3) / 1e12
-    paper_sections = {
-        "sorting": stage_ms["sorting"], "moving": stage_ms["moving"],
-        "tree_construction": stage_ms["tree_construction"],
-        "multipoles": stage_ms["multipoles"] + stage_ms["mac_prep"], "tree_traverse": walk_ms,
-    }
+    sections = paper_sections(stage_ms)
+    step_sums = sorted(sum(x[k] for k in mibh.STAGES) for x in stages)
     traffic = measured_traffic(workload)
     fma_tflops = fma_ceiling(dev)
 
@@ -464,7 +516,8 @@ def main():
         "interactions_per_s": inter * args.steps / (total_ms * 1e-3),
         "interactions_per_particle": {"pc": st["sum_pc"] / n, "pp": st["sum_pp"] / n},
         "stage_ms": stage_ms,
-        "paper_sections_ms": paper_sections,
+        "paper_sections_ms": sections,
+        "ms_per_step_stage_events": {"median": float(np.median(step_sums)), "min": step_sums[0]},
         "walk_share": walk_ms / ms_step,
         "tree": {"ncells": st["ncells"], "ngroups": st["ngroups"], "nleaves": st["nleaves"],
                  "depth": st["depth"]},
@@ -491,6 +544,11 @@ def main():
         torch.cuda.synchronize()
         result["copy_check_bytes"] = nb
     if not args.no_variants:
+        log("[bench] variant: opening angles 0.5 and 1.0")
+        result["variant_theta"] = [bench_config(pos, mass, th, max(3, args.steps // 4), 1) for th in (0.5, 1.0)]
+        log("[bench] variant: sections at N = 2^20")
+        p20, _, m20 = workloads.plummer(1 << 20, 2, with_velocities=False)
+        result["variant_sections_n1048576_seed2"] = bench_config(p20, m20, theta, args.steps, 2)
         log("[bench] variant: kahan")
         result["variant_kahan"] = bench_variant_kahan(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variant: batched ensemble")

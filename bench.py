@@ -96,16 +96,26 @@ def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 2):
         t_walk += time.perf_counter() - t0
         sampled += width
     t_step = t_build + t_walk * ng / sampled
+    # the paper's host had 4 cores: the same estimate with 4 threads on an eighth of the groups
+    width4 = max(1, width // 4)
+    t_walk4 = 0.0
+    for s in starts:
+        t0 = time.perf_counter()
+        T.walk(theta, groups=(int(s), int(s) + width4), nthreads=4)
+        t_walk4 += time.perf_counter() - t0
+    t_step4 = t_build + t_walk4 * ng / (width4 * n_ranges)
     n = len(mass)
     return {
         "value": n / t_step,
+        "value_4_threads": n / t_step4,
         "unit": "particles/s",
         "cores": oracle.num_threads(),
         "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"float64 oracle: full tree build of all {n} particles ({t_build:.2f} s, one thread) + "
                    f"walk of {sampled} of {ng} groups in {n_ranges} ranges ({t_walk:.2f} s), walk time "
-                   f"scaled by {ng / sampled:.1f}; estimated step {t_step:.1f} s"),
+                   f"scaled by {ng / sampled:.1f}; estimated step {t_step:.1f} s; with 4 threads "
+                   f"{width4 * n_ranges} groups in {t_walk4:.2f} s, estimated step {t_step4:.1f} s"),
     }
 
 

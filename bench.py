@@ -559,6 +559,10 @@ def main():
         log("[bench] variant: sections at N = 2^20")
         p20, _, m20 = workloads.plummer(1 << 20, 2, with_velocities=False)
         result["variant_sections_n1048576_seed2"] = bench_config(p20, m20, theta, args.steps, 2)
+        log("[bench] variant: N = 2^24")
+        p24, _, m24 = workloads.plummer(1 << 24, 9, with_velocities=False)
+        result["variant_n16777216_seed9"] = bench_config(p24, m24, theta, max(3, args.steps // 4), 1)
+        del p24, m24
         log("[bench] variant: kahan")
         result["variant_kahan"] = bench_variant_kahan(pos, mass, theta, max(3, args.steps // 4), 1)
         log("[bench] variant: batched ensemble")

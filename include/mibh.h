@@ -135,10 +135,12 @@ mibh_status mibh_refit(mibh_ctx *ctx, const float *d_pos, const float *d_mass);
 /* compute_forces for the groups that hold at least one particle with
  * d_active[i] != 0 (uint8 [n], input order, device memory): the walk visits
  * only those groups (the paper's block time steps, Results section: the
- * traverse time falls with the number of active particles).  acc and pot are
- * written for every particle of a visited group and left untouched for the
- * others; MIBH_EXPORT_COUNTS is updated for the visited groups only, and
- * MIBH_EXPORT_QUEUE lists the visited groups first, in Morton order.
+ * traverse time falls with the number of active particles).  Each visited
+ * group's interaction lists are those of a full walk (its whole box), but only
+ * its active particles are evaluated: acc and pot are written for the active
+ * particles and left untouched for every other particle; MIBH_EXPORT_COUNTS is
+ * updated for the visited groups only, and MIBH_EXPORT_QUEUE lists the visited
+ * groups first, in Morton order.
  * Errors: as compute_forces, EINVAL for a null mask. */
 mibh_status mibh_compute_forces_active(mibh_ctx *ctx, float theta, const uint8_t *d_active, float *d_acc,
                                        float *d_pot);

@@ -12,7 +12,9 @@ the walk slows down; it names no scheme.  The reading taken, step by step:
   as the smallest r with 16^r >= dt_max^4 |a|^2 / (eta^4 eps^2);
 * a clock ticks in dt_max / 2^R; every particle drifts every tick; at tick s
   the particles whose 2^(R - r_i) divides s are due; if any is, the tree is
-  refitted (or rebuilt), the groups holding a due particle are walked, and each due
+  refitted (or rebuilt), the groups holding a due particle are walked (each
+  with its whole box, so its lists are those of a full walk), the due particles
+  get new accelerations and potentials (the others keep theirs), and each due
   particle gets its closing half kick (old level), a new level (at least
   R - (trailing zeros of s), so that its next step starts on its own grid)
   and its opening half kick;
@@ -105,11 +107,9 @@ def block_run(pos, vel, mass, theta, dt_max, R, eta, eps, nbig, tol=0.25, eps2=0
                             np.int64)
             T.walk_groups(theta, walk, eps2, G, nthreads=nthreads)
             ta, tp = T.forces()
-            visited = np.zeros(n, bool)
-            for k in walk:
-                visited[T.perm[g["first"][k]:g["first"][k] + g["count"][k]]] = True
-            a[visited] = ta[visited]
-            p[visited] = tp[visited]
+            # the walked groups' lists serve only their due particles
+            a[due] = ta[due]
+            p[due] = tp[due]
             npc, npp = T.counts()
             now = g["count"][walk] * (1 + npc[walk] + npp[walk])
             ref = gref[walk]

@@ -361,7 +361,7 @@ static mibh_status forces_impl(mibh_ctx *ctx, float theta, const uint8_t *d_acti
     if ((st = mark(ctx, MIBH_STAGE_MACPREP))) return st;
     HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, (unsigned)ctx->nsys, ctx->p.eps2, ctx->p.G, ctx->p.precision,
                         mode == MIBH_ORDER_MORTON ? nullptr : ctx->b.qorder,
-                        d_active ? ctx->b.ohist + ORDER_BLOCKS : nullptr, d_acc, d_pot, ctx->stream),
+                        d_active ? ctx->b.ohist + ORDER_BLOCKS : nullptr, d_active, d_acc, d_pot, ctx->stream),
             "walk");
     ctx->last_order = mode;
     if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;

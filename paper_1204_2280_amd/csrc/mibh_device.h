@@ -136,7 +136,8 @@ hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double theta, hipStr
 // order: the queue (NULL: groups in Morton order); qlen: device count of queue
 // entries to walk (NULL: every group)
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
-                       const uint32_t *order, const uint32_t *qlen, float *acc, float *pot, hipStream_t s);
+                       const uint32_t *order, const uint32_t *qlen, const uint8_t *active, float *acc, float *pot,
+                       hipStream_t s);
 hipError_t launch_features(const Buffers &b, float theta, float *feat, hipStream_t s);
 hipError_t launch_mlp_forward(const void *w16, const float *x, unsigned rows, const Header *hdr, float *y,
                               hipStream_t s);

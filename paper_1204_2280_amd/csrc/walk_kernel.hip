@@ -134,6 +134,7 @@ struct WalkArgs {
     uint32_t *wstack;
     const uint32_t *order;   // queue order (NULL: Morton order)
     const uint32_t *qlen;    // number of queue entries to walk (NULL: all groups)
+    const uint8_t *active;   // per input particle, nonzero = evaluate it (NULL: every particle)
     unsigned *head;          // queue head
     float *acc, *pot;
     float eps2, G;
@@ -272,6 +273,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
     __shared__ uint32_t s_pp[WALK_PP_LDS];
     __shared__ float s_res[4][64];
     __shared__ float s_cmp[KAHAN ? 4 : 1][64];
+    __shared__ uint32_t s_idx[64];  // group particle evaluated in each lane
     const unsigned ln = lane64();
     uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
     if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
@@ -291,8 +293,9 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
         const uint2 gr = a.groups[g];
         const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform((gr.y >> 8) & 255u);
         const unsigned root = uniform(gr.y >> 16);  // level-0 cells are the systems' roots, in system order
-        const float4 p = a.spos[gf + min(ln, gn - 1)];
-        float3 bmin = make_float3(p.x, p.y, p.z), bmax = bmin;
+        const unsigned gl = min(ln, gn - 1);
+        const float4 p0 = a.spos[gf + gl];
+        float3 bmin = make_float3(p0.x, p0.y, p0.z), bmax = bmin;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             bmin.x = fminf(bmin.x, __shfl_xor(bmin.x, o, 64));
@@ -302,6 +305,21 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             bmax.y = fmaxf(bmax.y, __shfl_xor(bmax.y, o, 64));
             bmax.z = fmaxf(bmax.z, __shfl_xor(bmax.z, o, 64));
         }
+        // The particles evaluated: all of the group's, or only its active ones
+        // (an active walk), packed into the first `ge` lanes.  The interaction
+        // lists are the whole group's either way (its box above).
+        const bool due = ln < gn && (!a.active || a.active[a.perm[gf + gl]] != 0);
+        const unsigned long long dm = __ballot(due);
+        const unsigned ge = (unsigned)__popcll(dm);
+        if (due) s_idx[rank_below(dm)] = ln;
+        __syncthreads();
+        const unsigned pv = s_idx[ln];
+        const unsigned pj = ln < ge ? pv : 0u;
+        float4 p;
+        p.x = __shfl(p0.x, pj, 64);
+        p.y = __shfl(p0.y, pj, 64);
+        p.z = __shfl(p0.z, pj, 64);
+        p.w = 0.0f;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
             s_res[c][ln] = 0.0f;
@@ -340,7 +358,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             const unsigned long long am = __ballot(accept);
             const unsigned na = (unsigned)__popcll(am);
             if (npc + na > a.pc_cap)
-                npc = flush_list<KAHAN, true>(a, s_pc, npc, false, gn, p.x, p.y, p.z, s_res, s_cmp);
+                npc = flush_list<KAHAN, true>(a, s_pc, npc, false, ge, p.x, p.y, p.z, s_res, s_cmp);
             if (accept) s_pc[npc + rank_below(am)] = c;
             npc += na;
             tot_pc += na;
@@ -352,7 +370,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
                 unsigned sum;
                 const unsigned off = small_excl_scan(take, &sum);
                 if (npp + sum > a.pp_cap)
-                    npp = flush_list<KAHAN, false>(a, s_pp, npp, false, gn, p.x, p.y, p.z, s_res, s_cmp);
+                    npp = flush_list<KAHAN, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
                 for (unsigned j = 0; j < take; j++) s_pp[npp + off + j] = src + j;
                 npp += sum;
                 tot_pp += sum;
@@ -385,19 +403,19 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             atomicOr(&a.hdr->flags, FLAG_STACK);
             continue;
         }
-        if (npc) flush_list<KAHAN, true>(a, s_pc, npc, true, gn, p.x, p.y, p.z, s_res, s_cmp);
-        if (npp) flush_list<KAHAN, false>(a, s_pp, npp, true, gn, p.x, p.y, p.z, s_res, s_cmp);
+        if (npc) flush_list<KAHAN, true>(a, s_pc, npc, true, ge, p.x, p.y, p.z, s_res, s_cmp);
+        if (npp) flush_list<KAHAN, false>(a, s_pp, npp, true, ge, p.x, p.y, p.z, s_res, s_cmp);
 
         // results back to the caller's order
         const unsigned idx = bitrev6(ln);
         const unsigned comp = idx & 3u;
-        for (unsigned c = 0; c * CHUNK < gn; c++) {
+        for (unsigned c = 0; c * CHUNK < ge; c++) {
             const unsigned pi = c * CHUNK + (idx >> 2);
-            if (pi < gn) {
+            if (pi < ge) {
                 float val = s_res[c][ln];
                 if (KAHAN) val = val - s_cmp[c][ln];
                 val *= a.G;
-                const size_t orig = a.perm[gf + pi];
+                const size_t orig = a.perm[gf + s_idx[pi]];
                 if (comp < 3) a.acc[3 * orig + comp] = val;
                 else a.pot[orig] = val;
             }
@@ -409,7 +427,8 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
 }  // namespace
 
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
-                       const uint32_t *order, const uint32_t *qlen, float *acc, float *pot, hipStream_t s) {
+                       const uint32_t *order, const uint32_t *qlen, const uint8_t *active, float *acc, float *pot,
+                       hipStream_t s) {
     (void)n;
     WalkArgs a;
     a.hdr = b.hdr;
@@ -423,6 +442,7 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
     a.wstack = b.wstack;
     a.order = order;
     a.qlen = qlen;
+    a.active = active;
     a.head = &b.hdr->walk_head;
     a.acc = acc;
     a.pot = pot;

@@ -4,9 +4,9 @@
 * Refit after a drift: moved particles, float64 moments, delta, l', MAC data
   and interaction counts bit-exact; forces within 1e-5 at p99.
 * Active walk: only the groups holding an active particle are visited; their
-  counts are bit-exact and their particles' forces within 1e-5 at p99 of the
-  oracle's walk of the same groups; every other particle's outputs are
-  untouched.
+  counts are bit-exact and the active particles' forces within 1e-5 at p99 of
+  the oracle's walk of the same groups; every other particle's outputs, in a
+  visited group or not, are untouched.
 """
 import numpy as np
 import pytest
@@ -116,9 +116,12 @@ def test_active_walk_matches_oracle(orc):
         visited[T.perm[g["first"][k]:g["first"][k] + g["count"][k]]] = True
     a, p = T.forces()
     ga, gp = acc.cpu().numpy(), pot.cpu().numpy()
-    assert p99(rel_err(ga[visited], a[visited])) <= TOL_P99
-    assert p99(rel_err(gp[visited], p[visited])) <= TOL_P99
-    assert np.all(ga[~visited] == 7.0) and np.all(gp[~visited] == 7.0)
+    on = active != 0
+    assert np.all(visited[on])
+    print(f"[gpu] active walk: {int((visited & ~on).sum())} inactive particles in visited groups", flush=True)
+    assert p99(rel_err(ga[on], a[on])) <= TOL_P99
+    assert p99(rel_err(gp[on], p[on])) <= TOL_P99
+    assert np.all(ga[~on] == 7.0) and np.all(gp[~on] == 7.0)
     counts = ctx.export("counts").cpu().numpy().view(np.uint32).astype(np.int64)
     npc, npp = T.counts()
     np.testing.assert_array_equal(counts[gsel, 0], npc[gsel])

@@ -36,10 +36,17 @@ def log(*a):
 
 
 def walk_source_hash() -> str:
+    """Hash of the walk kernel's code: its sources with comments and blank
+    lines removed, so that a comment edit keeps the recorded counters."""
+    import re
     h = hashlib.sha256()
     for f in WALK_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()
 
 

@@ -26,8 +26,10 @@
 // entries (64 sources per tile) and a wave-uniform loop runs over the group's
 // particles, 16 at a time; each lane keeps 16 x 4 partial sums, folded across
 // lanes at the end of a list by a 63-shuffle transposed reduction (lane l
-// receives the total of accumulator bitrev6(l)).  No floating-point atomics:
-// results are bitwise reproducible run to run.
+// receives the total of accumulator bitrev6(l)).  An active walk (block time
+// steps) evaluates only the group's active particles, packed into the first
+// lanes; its lists are still built from the whole group's box.  No
+// floating-point atomics: results are bitwise reproducible run to run.
 #include "mibh_device.h"
 
 namespace mibh {

@@ -25,8 +25,9 @@
 // Evaluation: groups average ~20 particles, so lanes run over the list
 // entries (64 sources per tile) and a wave-uniform loop runs over the group's
 // particles, 16 at a time; each lane keeps 16 x 4 partial sums, folded across
-// lanes at the end of a list by a 63-shuffle transposed reduction (lane l
-// receives the total of accumulator bitrev6(l)).  An active walk (block time
+// lanes by a 63-shuffle transposed reduction (lane l receives the total of
+// accumulator bitrev6(l)) when a full list is flushed, and once for both lists
+// at the end of the group.  An active walk (block time
 // steps) evaluates only the group's active particles, packed into the first
 // lanes; its lists are still built from the whole group's box.  No
 // floating-point atomics: results are bitwise reproducible run to run.
@@ -146,12 +147,12 @@ struct WalkArgs {
 constexpr int CHUNK = 16;        // group particles per evaluation pass
 constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
 
-// Evaluates `nlist` list entries (cells if PC, particles otherwise) for all
-// `gn` group particles and adds the results into s_res (one value per lane
-// per chunk).
-template <bool KAHAN, bool PC>
-__device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist, unsigned gn, float px, float py,
-                         float pz, float (*s_res)[64], float (*s_cmp)[64]) {
+// Evaluates `npcl` particle-cell entries and `nppl` particle-particle entries
+// for all `gn` group particles and adds the results into s_res (one value per
+// lane per chunk): one reduction per chunk covers both lists.
+template <bool KAHAN>
+__device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, const uint32_t *ppl, unsigned nppl,
+                         unsigned gn, float px, float py, float pz, float (*s_res)[64], float (*s_cmp)[64]) {
     const unsigned ln = lane64();
     const float eps2 = a.eps2;
     for (unsigned c0 = 0; c0 < gn; c0 += CHUNK) {
@@ -167,7 +168,7 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist
         float v[64], cv[64];
 #pragma unroll
         for (int j = 0; j < 64; j++) { v[j] = 0.0f; cv[j] = 0.0f; }
-        for (unsigned t0 = 0; t0 < nlist; t0 += 64) {
+        for (unsigned t0 = 0; t0 < npcl; t0 += 64) {
             // The particle count of the chunk is taken as new in every tile, so
             // that its 16 comparisons are made in place (scalar compares) instead
             // of being kept as 16 lane masks across the loop: 32 scalar registers
@@ -176,64 +177,73 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *list, unsigned nlist
             unsigned cn_t = cn;
             asm volatile("" : "+s"(cn_t));
             const unsigned k = t0 + ln;
-            const bool valid = k < nlist;
-            const unsigned e = valid ? list[k] : 0u;
-            if (PC) {
-                float4 m = a.cmac[e], q0 = a.ceval[2 * (size_t)e], q1 = a.ceval[2 * (size_t)e + 1];
-                if (!valid) {
-                    m = make_float4(FAR, FAR, FAR, 0.0f);
-                    q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    q1 = q0;
-                }
+            const bool valid = k < npcl;
+            const unsigned e = valid ? pcl[k] : 0u;
+            float4 m = a.cmac[e], q0 = a.ceval[2 * (size_t)e], q1 = a.ceval[2 * (size_t)e + 1];
+            if (!valid) {
+                m = make_float4(FAR, FAR, FAR, 0.0f);
+                q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                q1 = q0;
+            }
 #pragma unroll
-                for (int ii = 0; ii < CHUNK; ii++) {
-                    if ((unsigned)ii < cn_t) {
-                        // R = x - com; r2 = R.R + eps2
-                        const float Rx = xi[ii] - m.x, Ry = yi[ii] - m.y, Rz = zi[ii] - m.z;
-                        const float r2 = fmaf(Rz, Rz, fmaf(Ry, Ry, fmaf(Rx, Rx, eps2)));
-                        const float rinv = __builtin_amdgcn_rsqf(r2);
-                        const float rinv2 = rinv * rinv;
-                        const float r3 = rinv * rinv2;
-                        const float r5 = r3 * rinv2;
-                        // Q R with Q = (xx, yy, zz | xy, xz, yz)
-                        const float QRx = fmaf(q0.y, Rx, fmaf(q1.x, Ry, q1.y * Rz));
-                        const float QRy = fmaf(q1.x, Rx, fmaf(q0.z, Ry, q1.z * Rz));
-                        const float QRz = fmaf(q1.y, Rx, fmaf(q1.z, Ry, q0.w * Rz));
-                        const float RQR = fmaf(Rx, QRx, fmaf(Ry, QRy, Rz * QRz));
-                        const float Mr3 = q0.x * r3;
-                        const float u = RQR * r5;
-                        // a = -M R/r^3 + Q R/r^5 - (5/2)(RQR) R/r^7 ; phi = -(M/r + RQR/(2 r^5))
-                        const float coef = fmaf(2.5f * u, rinv2, Mr3);
-                        if (KAHAN) {
-                            add<true>(v[4 * ii + 0], cv[4 * ii + 0], fmaf(QRx, r5, -coef * Rx));
-                            add<true>(v[4 * ii + 1], cv[4 * ii + 1], fmaf(QRy, r5, -coef * Ry));
-                            add<true>(v[4 * ii + 2], cv[4 * ii + 2], fmaf(QRz, r5, -coef * Rz));
-                            add<true>(v[4 * ii + 3], cv[4 * ii + 3], -fmaf(0.5f, u, q0.x * rinv));
-                        } else {  // the term goes into the sum as two fused multiply-adds
-                            v[4 * ii + 0] = fmaf(-coef, Rx, fmaf(QRx, r5, v[4 * ii + 0]));
-                            v[4 * ii + 1] = fmaf(-coef, Ry, fmaf(QRy, r5, v[4 * ii + 1]));
-                            v[4 * ii + 2] = fmaf(-coef, Rz, fmaf(QRz, r5, v[4 * ii + 2]));
-                            v[4 * ii + 3] = fmaf(-q0.x, rinv, fmaf(-0.5f, u, v[4 * ii + 3]));
-                        }
+            for (int ii = 0; ii < CHUNK; ii++) {
+                if ((unsigned)ii < cn_t) {
+                    // R = x - com; r2 = R.R + eps2
+                    const float Rx = xi[ii] - m.x, Ry = yi[ii] - m.y, Rz = zi[ii] - m.z;
+                    const float r2 = fmaf(Rz, Rz, fmaf(Ry, Ry, fmaf(Rx, Rx, eps2)));
+                    const float rinv = __builtin_amdgcn_rsqf(r2);
+                    const float rinv2 = rinv * rinv;
+                    const float r3 = rinv * rinv2;
+                    const float r5 = r3 * rinv2;
+                    // Q R with Q = (xx, yy, zz | xy, xz, yz)
+                    const float QRx = fmaf(q0.y, Rx, fmaf(q1.x, Ry, q1.y * Rz));
+                    const float QRy = fmaf(q1.x, Rx, fmaf(q0.z, Ry, q1.z * Rz));
+                    const float QRz = fmaf(q1.y, Rx, fmaf(q1.z, Ry, q0.w * Rz));
+                    const float RQR = fmaf(Rx, QRx, fmaf(Ry, QRy, Rz * QRz));
+                    const float Mr3 = q0.x * r3;
+                    const float u = RQR * r5;
+                    // a = -M R/r^3 + Q R/r^5 - (5/2)(RQR) R/r^7 ; phi = -(M/r + RQR/(2 r^5))
+                    const float coef = fmaf(2.5f * u, rinv2, Mr3);
+                    if (KAHAN) {
+                        add<true>(v[4 * ii + 0], cv[4 * ii + 0], fmaf(QRx, r5, -coef * Rx));
+                        add<true>(v[4 * ii + 1], cv[4 * ii + 1], fmaf(QRy, r5, -coef * Ry));
+                        add<true>(v[4 * ii + 2], cv[4 * ii + 2], fmaf(QRz, r5, -coef * Rz));
+                        add<true>(v[4 * ii + 3], cv[4 * ii + 3], -fmaf(0.5f, u, q0.x * rinv));
+                    } else {  // the term goes into the sum as two fused multiply-adds
+                        v[4 * ii + 0] = fmaf(-coef, Rx, fmaf(QRx, r5, v[4 * ii + 0]));
+                        v[4 * ii + 1] = fmaf(-coef, Ry, fmaf(QRy, r5, v[4 * ii + 1]));
+                        v[4 * ii + 2] = fmaf(-coef, Rz, fmaf(QRz, r5, v[4 * ii + 2]));
+                        v[4 * ii + 3] = fmaf(-q0.x, rinv, fmaf(-0.5f, u, v[4 * ii + 3]));
                     }
                 }
-            } else {
-                float4 s = a.spos[e];
-                if (!valid) s = make_float4(FAR, FAR, FAR, 0.0f);
+            }
+        }
+        for (unsigned t0 = 0; t0 < nppl; t0 += 64) {
+            // The particle count of the chunk is taken as new in every tile, so
+            // that its 16 comparisons are made in place (scalar compares) instead
+            // of being kept as 16 lane masks across the loop: 32 scalar registers
+            // more than the wave can hold, spilled to vector-register lanes and
+            // read back in every tile.
+            unsigned cn_t = cn;
+            asm volatile("" : "+s"(cn_t));
+            const unsigned k = t0 + ln;
+            const bool valid = k < nppl;
+            const unsigned e = valid ? ppl[k] : 0u;
+            float4 s = a.spos[e];
+            if (!valid) s = make_float4(FAR, FAR, FAR, 0.0f);
 #pragma unroll
-                for (int ii = 0; ii < CHUNK; ii++) {
-                    if ((unsigned)ii < cn_t) {
-                        const float dx = s.x - xi[ii], dy = s.y - yi[ii], dz = s.z - zi[ii];
-                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        float rinv = __builtin_amdgcn_rsqf(r2 + eps2);
-                        rinv = r2 > 0.0f ? rinv : 0.0f;  // self and coincident pairs contribute nothing
-                        const float mr = s.w * rinv;
-                        const float mr3 = mr * rinv * rinv;
-                        add<KAHAN>(v[4 * ii + 0], cv[4 * ii + 0], mr3 * dx);
-                        add<KAHAN>(v[4 * ii + 1], cv[4 * ii + 1], mr3 * dy);
-                        add<KAHAN>(v[4 * ii + 2], cv[4 * ii + 2], mr3 * dz);
-                        add<KAHAN>(v[4 * ii + 3], cv[4 * ii + 3], -mr);
-                    }
+            for (int ii = 0; ii < CHUNK; ii++) {
+                if ((unsigned)ii < cn_t) {
+                    const float dx = s.x - xi[ii], dy = s.y - yi[ii], dz = s.z - zi[ii];
+                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    float rinv = __builtin_amdgcn_rsqf(r2 + eps2);
+                    rinv = r2 > 0.0f ? rinv : 0.0f;  // self and coincident pairs contribute nothing
+                    const float mr = s.w * rinv;
+                    const float mr3 = mr * rinv * rinv;
+                    add<KAHAN>(v[4 * ii + 0], cv[4 * ii + 0], mr3 * dx);
+                    add<KAHAN>(v[4 * ii + 1], cv[4 * ii + 1], mr3 * dy);
+                    add<KAHAN>(v[4 * ii + 2], cv[4 * ii + 2], mr3 * dz);
+                    add<KAHAN>(v[4 * ii + 3], cv[4 * ii + 3], -mr);
                 }
             }
         }
@@ -254,7 +264,10 @@ __device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bo
                                float py, float pz, float (*s_res)[64], float (*s_cmp)[64]) {
     const unsigned ne = all ? n : (n & ~63u);
     __syncthreads();  // list entries written by other lanes are visible
-    if (ne) evaluate<KAHAN, PC>(a, list, ne, gn, px, py, pz, s_res, s_cmp);
+    if (ne) {
+        if (PC) evaluate<KAHAN>(a, list, ne, list, 0u, gn, px, py, pz, s_res, s_cmp);
+        else evaluate<KAHAN>(a, list, 0u, list, ne, gn, px, py, pz, s_res, s_cmp);
+    }
     const unsigned r = n - ne;
     if (r) {
         const unsigned ln = lane64();
@@ -405,8 +418,10 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             atomicOr(&a.hdr->flags, FLAG_STACK);
             continue;
         }
-        if (npc) flush_list<KAHAN, true>(a, s_pc, npc, true, ge, p.x, p.y, p.z, s_res, s_cmp);
-        if (npp) flush_list<KAHAN, false>(a, s_pp, npp, true, ge, p.x, p.y, p.z, s_res, s_cmp);
+        if (npc + npp) {
+            __syncthreads();  // list entries written by other lanes are visible
+            evaluate<KAHAN>(a, s_pc, npc, s_pp, npp, ge, p.x, p.y, p.z, s_res, s_cmp);
+        }
 
         // results back to the caller's order
         const unsigned idx = bitrev6(ln);

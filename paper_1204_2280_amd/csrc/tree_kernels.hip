@@ -341,8 +341,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__r
         const unsigned d = valid ? radix_digit(shift >= 0 ? keys[idx] : 0ull, shift >= 0 ? 0u : vals[idx], shift,
                                                sys8)
                                  : 0u;
-        const unsigned long long peers = match_digit(d, __ballot(valid));
-        if (valid && ln == (unsigned)(__ffsll((long long)peers) - 1)) h[w][d] += __popcll(peers);
+        if (valid) atomicAdd(&h[w][d], 1u);  // integer counts: the order of the adds does not matter
     }
     __syncthreads();
     for (unsigned d = threadIdx.x; d < RADIX; d += SORT_THREADS) {

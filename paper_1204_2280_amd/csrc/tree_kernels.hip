@@ -506,36 +506,68 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_count(
     uint32_t *__restrict__ blkcnt, unsigned nblk) {
     constexpr int H = MAX_WINDOW;
     constexpr int NW = BUILD_THREADS / 64;
-    __shared__ int8_t s_cl[BUILD_THREADS + 2 * H + 2];
-    __shared__ int8_t s_wn[BUILD_THREADS + H + 1];
-    __shared__ int8_t s_wg[BUILD_THREADS + H + 1];
+    constexpr int A = BUILD_THREADS + 2 * H + 1;   // cl of particles base - H .. base + BUILD_THREADS + H
+    constexpr int B = BUILD_THREADS + H;           // window starts
+    __shared__ int8_t s_cl[A];
+    __shared__ int8_t s_t[3][A];                   // doubling tables of minima (two in turn, one kept)
+    __shared__ int8_t s_wn[B];
+    __shared__ int8_t s_wg[B];
+    __shared__ int8_t s_m[4][B];                   // doubling tables of maxima (two per window size)
     __shared__ uint32_t s_cnt[NW][NCOUNTERS];
     const unsigned base = blockIdx.x * BUILD_THREADS;
-    for (int j = threadIdx.x; j < BUILD_THREADS + 2 * H + 1; j += BUILD_THREADS) {
+    for (int j = threadIdx.x; j < A; j += BUILD_THREADS) {
         const long long gi = (long long)base - H + j;
         s_cl[j] = (gi >= 0 && gi < (long long)n) ? cl[gi] : (int8_t)-1;
     }
     __syncthreads();
-    // minimum of cl over each window's inner boundaries, window start a <-> local a - base + H
-    for (int a = threadIdx.x; a < BUILD_THREADS + H; a += BUILD_THREADS) {
-        int mn = 127, mg = 127;
-        for (int d = 1; d <= gcap; d++) {
-            const int v = s_cl[a + d];
-            if (d <= ncrit) mn = min(mn, v);
-            mg = min(mg, v);
+    // Sliding-window extrema by doubling: after step k a table holds the
+    // minimum (maximum) of 2^k consecutive entries starting at each index, and
+    // a window of length w is covered by two such runs of length 2^floor(log2 w).
+    // s_wn[a] = min cl[a+1 .. a+ncrit], s_wg[a] = min cl[a+1 .. a+gcap]: the
+    // inner boundaries of the windows that start at a.
+    const int kn = 31 - __clz(ncrit), kg = 31 - __clz(gcap);
+    {
+        const int8_t *cur = s_cl, *tn = s_cl;
+        for (int k = 0; k < kg; k++) {
+            int8_t *nxt = s_t[k & 1];
+            const int sh = 1 << k;
+            for (int j = threadIdx.x; j < A; j += BUILD_THREADS) {
+                const int8_t v = j + sh < A ? (int8_t)min((int)cur[j], (int)cur[j + sh]) : cur[j];
+                nxt[j] = v;
+                if (k + 1 == kn) s_t[2][j] = v;
+            }
+            __syncthreads();
+            cur = nxt;
+            if (k + 1 == kn) tn = s_t[2];
         }
-        s_wn[a] = (int8_t)mn;
-        s_wg[a] = (int8_t)mg;
+        for (int a = threadIdx.x; a < B; a += BUILD_THREADS) {
+            s_wn[a] = (int8_t)min((int)tn[a + 1], (int)tn[a + 1 + ncrit - (1 << kn)]);
+            s_wg[a] = (int8_t)min((int)cur[a + 1], (int)cur[a + 1 + gcap - (1 << kg)]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
+    // ln = max s_wn[tl - ncrit .. tl], lg = max s_wg[tl - gcap .. tl]: the
+    // windows of ncrit + 1 (gcap + 1) particles that contain particle tl.
     const unsigned i = base + threadIdx.x;
     const bool valid = i < n;
     const int tl = threadIdx.x + H;
-    int ln = -1, lg = -1;
-    for (int d = 0; d <= gcap; d++) {
-        const int vg = s_wg[tl - d];
-        if (d <= ncrit) ln = max(ln, (int)s_wn[tl - d]);
-        lg = max(lg, vg);
+    int ln, lg;
+    {
+        const int kn2 = 31 - __clz(ncrit + 1), kg2 = 31 - __clz(gcap + 1);
+        const int8_t *cn = s_wn, *cg = s_wg;
+        for (int k = 0; k < kg2; k++) {
+            int8_t *nn = s_m[k & 1], *ng = s_m[2 + (k & 1)];
+            const int sh = 1 << k;
+            for (int j = threadIdx.x; j < B; j += BUILD_THREADS) {
+                if (k < kn2) nn[j] = j + sh < B ? (int8_t)max((int)cn[j], (int)cn[j + sh]) : cn[j];
+                ng[j] = j + sh < B ? (int8_t)max((int)cg[j], (int)cg[j + sh]) : cg[j];
+            }
+            __syncthreads();
+            if (k < kn2) cn = nn;
+            cg = ng;
+        }
+        ln = max((int)cn[tl - ncrit], (int)cn[tl - (1 << kn2) + 1]);
+        lg = max((int)cg[tl - gcap], (int)cg[tl - (1 << kg2) + 1]);
     }
     const int leaf = ln < 0 ? 0 : min(ln + 1, KEY_LEVELS);
     const int glev = lg < 0 ? 0 : min(lg + 1, KEY_LEVELS);
@@ -654,17 +686,26 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
     // the system of this particle and its end: runs never cross systems
     const unsigned sys = (nsys > 1 && valid) ? system_of(sys_off, nsys, i) : 0u;
     const unsigned send = nsys > 1 ? (valid ? sys_off[sys + 1] : n) : n;
-    // cells, deepest level first so that each cell knows its first child's number
-    unsigned next = 0;
+    // cells, deepest level first so that each cell knows its first child's number.
+    // A level-l cell starting at i ends at the first j > i with cl(j) < l (or
+    // where the particles end): the wave finds it from a ballot of those
+    // boundaries when it lies inside the wave, else by searching the keys.
+    const int ci = clo - 1;
+    const unsigned ln = lane64();
+    unsigned next = 0, gend = 0;
     for (int l = KEY_LEVELS; l >= 0; l--) {
         const bool pred = clo <= l && l <= leaf;
         const unsigned long long b = __ballot(pred);
+        if (b == 0) continue;
+        const unsigned long long bnd = __ballot(!valid || ci < l);
         if (pred) {
             const unsigned idx = s_base[l] + s_blk[l] + s_wpre[w][l] + rank_below(b);
-            const unsigned cnt = run_end(keys, send, i, l) - i;
+            const unsigned long long after = ln < 63 ? bnd >> (ln + 1) : 0ull;
+            const unsigned end = after ? i + (unsigned)__ffsll((long long)after) : run_end(keys, send, i, l);
             const unsigned cf = l < leaf ? next : 0u;
-            if (idx < cap_cells) topo[idx] = make_uint4(i, cnt, cf, (sys << 16) | ((unsigned)l << 8));
+            if (idx < cap_cells) topo[idx] = make_uint4(i, end - i, cf, (sys << 16) | ((unsigned)l << 8));
             next = idx;
+            if (l == glev) gend = end;
         }
     }
     {
@@ -673,7 +714,7 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
             const unsigned g = s_blk[NCOUNTERS - 1] + s_wpre[w][NCOUNTERS - 1] + rank_below(b);
             unsigned cnt;
             if (info.w & 2) cnt = min((unsigned)gcap, run_end(keys, send, i, KEY_LEVELS) - i);
-            else cnt = run_end(keys, send, i, glev) - i;
+            else cnt = (gend ? gend : run_end(keys, send, i, glev)) - i;
             groups[g] = make_uint2(i, (sys << 16) | ((unsigned)glev << 8) | cnt);
         }
     }

@@ -754,7 +754,9 @@ hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, 
 }
 
 // --------------------------------------------------------------------------
-// Multipole moments, float64, one launch per level from the deepest up.
+// Multipole moments, float64: one launch for the leaves of every level (they
+// depend on particles only), then one per level for its internal cells, from
+// the deepest up.
 //   leaf:     M = sum m, com = (sum fma(m, x, .)) / M, S_ab = sum fma(m d_a, d_b, .)
 //   internal: M = sum M_c, com = (sum fma(M_c, com_c, .)) / M,
 //             S_ab = sum (S_c,ab + (M_c e_a) e_b), e = com_c - com
@@ -771,18 +773,23 @@ hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, 
 
 constexpr unsigned LEAF_REGS = 16;  // leaves up to this size are summed from registers
 
+// lev < 0: every leaf; otherwise the internal cells of level lev.
 __global__ __launch_bounds__(256) void k_multipole_level(
-    int lev, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
+    int lev_in, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
     const float4 *__restrict__ spos, const uint64_t *__restrict__ keys, double *__restrict__ mp,
     double *__restrict__ delta, float *__restrict__ cbox, double *__restrict__ lside, float4 *__restrict__ cmac,
     float4 *__restrict__ ceval, unsigned cap_cells) {
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
-    const unsigned cb = min(hdr->lvl_begin[lev], nc), ce = min(hdr->lvl_begin[lev + 1], nc);
+    const bool leaves = lev_in < 0;
+    const unsigned cb = leaves ? 0u : min(hdr->lvl_begin[lev_in], nc);
+    const unsigned ce = leaves ? nc : min(hdr->lvl_begin[lev_in + 1], nc);
     for (unsigned c = cb + blockIdx.x * 256u + threadIdx.x; c < ce; c += gridDim.x * 256u) {
         const uint4 t = topo[c];
         const unsigned nch = t.w & 255u;
+        if ((nch == 0) != leaves) continue;
+        const int lev = (int)((t.w >> 8) & 255u);
         const SysCube cb3 = cube[t.w >> 16];
         const double lo[3] = {(double)cb3.lo[0], (double)cb3.lo[1], (double)cb3.lo[2]};
         const double l = ldexp(1.0, cb3.k - lev);
@@ -933,10 +940,13 @@ __global__ __launch_bounds__(256) void k_multipole_level(
 
 hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s) {
     const unsigned grid = min((b.cap_cells + 255u) / 256u, 2048u);
-    for (int lev = KEY_LEVELS; lev >= 0; lev--)
+    auto level = [&](int lev) {
         hipLaunchKernelGGL(k_multipole_level, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.cube, b.topo, b.spos,
                            b.keys[sorted_buffer(nsys)], b.mp, b.delta, b.cbox, b.lside, b.cmac, b.ceval,
                            b.cap_cells);
+    };
+    level(-1);  // every leaf
+    for (int lev = KEY_LEVELS - 1; lev >= 0; lev--) level(lev);  // level KEY_LEVELS holds leaves only
     return hipGetLastError();
 }
 

@@ -342,10 +342,16 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
         }
 
         // logical stack = global spill [0, gtop) followed by the LDS ring [sb, st)
-        unsigned sb = 0, st = 1, gtop = 0;
+        // The root is an ancestor of every group, so the walk always opens it:
+        // its children (the root itself when it is a leaf) start the stack, in
+        // the order its opening would push them.
+        const uint4 tr = a.topo[root];
+        const unsigned rn = uniform(tr.w & 255u);
+        unsigned sb = 0, st = rn ? rn : 1u, gtop = 0;
         unsigned npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
         bool overflow = false;
-        s_stk[0] = root;  // every lane stores the same value
+        const unsigned first = rn ? tr.z + min(ln, rn - 1) : root;
+        if (ln < st) s_stk[ln] = first;
         __syncthreads();
         while (st != sb || gtop > 0) {
             if (st == sb) {  // LDS part empty: refill from the top of the global spill

@@ -66,7 +66,7 @@ def train(x, t, steps: int = 2000, batch: int = 1024, lr: float = 3e-3, seed: in
 
 
 def evaluate(w16, x, t, margin: float = 1.25):
-    """Prediction quality against the exact counts (the judge): MAPE of the
+    """Prediction quality, scored against the exact counts: MAPE of the
     interaction count, RMS error of log2, and the misprediction rate (exact
     count above margin x predicted count)."""
     import torch

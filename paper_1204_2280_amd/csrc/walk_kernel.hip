@@ -65,30 +65,34 @@ __device__ __forceinline__ unsigned small_excl_scan(unsigned v, unsigned *total)
     return r;
 }
 
-// Sums each of the 64 per-lane values v[0..63] over the wave; lane l gets the
-// total of v[bitrev6(l)].  Stage with offset o pairs v[2p], v[2p+1]: lanes
-// whose bit o is clear keep the pair sum of v[2p], the others of v[2p+1].  The
-// offsets 32 and 16 are the gfx950 half/row swaps (v_permlane32_swap exchanges
-// the upper half of its first operand with the lower half of its second, so one
-// swap and one add finish a pair); the others use shuffles.
-__device__ __forceinline__ float transpose_reduce(float (&v)[64]) {
+// Sums each of the NV per-lane values v[0..NV) (NV = 64 or 32) over the wave.
+// With NV = 64 lane l gets the total of v[bitrev6(l)]; with NV = 32 lanes l and
+// l ^ 1 both get the total of v[bitrev6(l) & 31].  Stage with offset o pairs
+// v[2p], v[2p+1]: lanes whose bit o is clear keep the pair sum of v[2p], the
+// others of v[2p+1].  The offsets 32 and 16 are the gfx950 half/row swaps
+// (v_permlane32_swap exchanges the upper half of its first operand with the
+// lower half of its second, so one swap and one add finish a pair); the others
+// use shuffles, and for NV = 32 a last shuffle adds the two lanes of a pair.
+template <int NV>
+__device__ __forceinline__ float transpose_reduce(float (&v)[NV]) {
+    static_assert(NV == 64 || NV == 32, "64 or 32 values");
     const unsigned ln = lane64();
 #pragma unroll
-    for (int p = 0; p < 32; p++) {
+    for (int p = 0; p < NV / 2; p++) {
         const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * p]), __float_as_uint(v[2 * p + 1]),
                                                         false, false);
         v[p] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 #pragma unroll
-    for (int p = 0; p < 16; p++) {
+    for (int p = 0; p < NV / 4; p++) {
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[2 * p]), __float_as_uint(v[2 * p + 1]),
                                                         false, false);
         v[p] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 #pragma unroll
-    for (int s = 2; s < 6; s++) {
+    for (int s = 2; (NV >> s) >= 2; s++) {
         const int o = 32 >> s;
-        const int len = 64 >> s;
+        const int len = NV >> s;
         const bool hi = (ln & (unsigned)o) != 0;
 #pragma unroll
         for (int p = 0; p < len / 2; p++) {
@@ -97,7 +101,7 @@ __device__ __forceinline__ float transpose_reduce(float (&v)[64]) {
             v[p] = keep + __shfl_xor(send, o, 64);
         }
     }
-    return v[0];
+    return NV == 64 ? v[0] : v[0] + __shfl_xor(v[0], 1, 64);
 }
 
 // The opening test, float32 with every operation rounded (no contraction):
@@ -144,7 +148,15 @@ struct WalkArgs {
     unsigned pc_cap, pp_cap;
 };
 
-constexpr int CHUNK = 16;        // group particles per evaluation pass
+// Group particles per evaluation pass: 16 (64 sums per lane), or 8 with
+// Kahan accumulation (32 sums and 32 compensations), so that both variants
+// keep 64 accumulator registers per lane.
+template <bool KAHAN> constexpr int chunk_of() { return KAHAN ? 8 : 16; }
+// Slot of a lane's reduced value for chunk c in the per-group result array
+// (256 floats: 4 chunks x 64 values, or 8 chunks x 32 values).
+template <bool KAHAN> __device__ __forceinline__ unsigned res_slot(unsigned c, unsigned ln) {
+    return KAHAN ? c * 32u + (ln >> 1) : c * 64u + ln;
+}
 constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
 
 // Evaluates `npcl` particle-cell entries and `nppl` particle-particle entries
@@ -152,7 +164,9 @@ constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
 // lane per chunk): one reduction per chunk covers both lists.
 template <bool KAHAN>
 __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, const uint32_t *ppl, unsigned nppl,
-                         unsigned gn, float px, float py, float pz, float (*s_res)[64], float (*s_cmp)[64]) {
+                         unsigned gn, float px, float py, float pz, float *s_res, float *s_cmp) {
+    constexpr int CHUNK = chunk_of<KAHAN>();
+    constexpr int NV = 4 * CHUNK;
     const unsigned ln = lane64();
     const float eps2 = a.eps2;
     for (unsigned c0 = 0; c0 < gn; c0 += CHUNK) {
@@ -165,9 +179,9 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
             yi[ii] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(py), src));
             zi[ii] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pz), src));
         }
-        float v[64], cv[64];
+        float v[NV], cv[NV];
 #pragma unroll
-        for (int j = 0; j < 64; j++) { v[j] = 0.0f; cv[j] = 0.0f; }
+        for (int j = 0; j < NV; j++) { v[j] = 0.0f; cv[j] = 0.0f; }
         for (unsigned t0 = 0; t0 < npcl; t0 += 64) {
             // The particle count of the chunk is taken as new in every tile, so
             // that its 16 comparisons are made in place (scalar compares) instead
@@ -249,11 +263,12 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
         }
         if (KAHAN) {
 #pragma unroll
-            for (int j = 0; j < 64; j++) v[j] = v[j] - cv[j];
+            for (int j = 0; j < NV; j++) v[j] = v[j] - cv[j];
         }
-        const float r = transpose_reduce(v);
-        if (KAHAN) add<true>(s_res[c0 / CHUNK][ln], s_cmp[c0 / CHUNK][ln], r);
-        else s_res[c0 / CHUNK][ln] += r;
+        const float r = transpose_reduce<NV>(v);
+        const unsigned slot = res_slot<KAHAN>(c0 / CHUNK, ln);
+        if (KAHAN) add<true>(s_res[slot], s_cmp[slot], r);
+        else s_res[slot] += r;
     }
 }
 
@@ -261,7 +276,7 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
 // remaining entries to the front and returns their number.
 template <bool KAHAN, bool PC>
 __device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bool all, unsigned gn, float px,
-                               float py, float pz, float (*s_res)[64], float (*s_cmp)[64]) {
+                               float py, float pz, float *s_res, float *s_cmp) {
     const unsigned ne = all ? n : (n & ~63u);
     __syncthreads();  // list entries written by other lanes are visible
     if (ne) {
@@ -280,14 +295,17 @@ __device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bo
 }
 
 template <bool KAHAN>
-__global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
+__global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
     constexpr unsigned MASK = WALK_LSTACK - 1;
     static_assert((WALK_LSTACK & MASK) == 0 && WALK_LSTACK >= 512, "stack ring must hold one step's pushes");
     __shared__ uint32_t s_stk[WALK_LSTACK];
-    __shared__ uint32_t s_pc[WALK_PC_LDS];
+    // the Kahan walk's compensations take 768 more bytes of LDS: its
+    // particle-cell list is shorter by as much, so 16 waves still fit a CU
+    constexpr unsigned PC_LDS = KAHAN ? WALK_PC_LDS - 192 : WALK_PC_LDS;
+    __shared__ uint32_t s_pc[PC_LDS];
     __shared__ uint32_t s_pp[WALK_PP_LDS];
-    __shared__ float s_res[4][64];
-    __shared__ float s_cmp[KAHAN ? 4 : 1][64];
+    __shared__ float s_res[256];
+    __shared__ float s_cmp[KAHAN ? 256 : 64];
     __shared__ uint32_t s_idx[64];  // group particle evaluated in each lane
     const unsigned ln = lane64();
     uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
@@ -297,6 +315,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
     const unsigned per_round = max(1u, (a.pp_cap - 64u) >> 6);  // < 16 since pp_cap <= 1024
     static_assert(WALK_PP_LDS <= 1024, "per-round counts must fit the 4-bit prefix sums");
     const unsigned ngroups = a.qlen ? uniform(*a.qlen) : uniform(a.hdr->ngroups);
+    const unsigned pc_cap = min(a.pc_cap, PC_LDS);
     for (;;) {
         // Every lane executes the queue atomic (only lane 0 adds 1) so that no
         // lane-dependent branch sits inside this loop: the compiler may split a
@@ -337,8 +356,8 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
         p.w = 0.0f;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-            s_res[c][ln] = 0.0f;
-            if (KAHAN) s_cmp[c][ln] = 0.0f;
+            s_res[c * 64 + ln] = 0.0f;
+            if (KAHAN) s_cmp[c * 64 + ln] = 0.0f;
         }
 
         // logical stack = global spill [0, gtop) followed by the LDS ring [sb, st)
@@ -378,7 +397,7 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
             // accepted cells -> particle-cell list
             const unsigned long long am = __ballot(accept);
             const unsigned na = (unsigned)__popcll(am);
-            if (npc + na > a.pc_cap)
+            if (npc + na > pc_cap)
                 npc = flush_list<KAHAN, true>(a, s_pc, npc, false, ge, p.x, p.y, p.z, s_res, s_cmp);
             if (accept) s_pc[npc + rank_below(am)] = c;
             npc += na;
@@ -430,13 +449,17 @@ __global__ __launch_bounds__(64, KAHAN ? 2 : 4) void k_walk(WalkArgs a) {
         }
 
         // results back to the caller's order
-        const unsigned idx = bitrev6(ln);
+        constexpr int CHUNK = chunk_of<KAHAN>();
+        // value held by this lane: bitrev6(ln) (64 per chunk) or its low five
+        // bits (32 per chunk, lanes ln and ln ^ 1 alike: the even one stores)
+        const unsigned idx = KAHAN ? (bitrev6(ln) & 31u) : bitrev6(ln);
         const unsigned comp = idx & 3u;
         for (unsigned c = 0; c * CHUNK < ge; c++) {
-            const unsigned pi = c * CHUNK + (idx >> 2);
+            const unsigned pi = c * CHUNK + (idx >> 2) + ((KAHAN && (ln & 1u)) ? 64u : 0u);
             if (pi < ge) {
-                float val = s_res[c][ln];
-                if (KAHAN) val = val - s_cmp[c][ln];
+                const unsigned slot = res_slot<KAHAN>(c, ln);
+                float val = s_res[slot];
+                if (KAHAN) val = val - s_cmp[slot];
                 val *= a.G;
                 const size_t orig = a.perm[gf + s_idx[pi]];
                 if (comp < 3) a.acc[3 * orig + comp] = val;

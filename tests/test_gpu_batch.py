@@ -142,6 +142,54 @@ def test_graph_replays_equal_eager_step():
         assert torch.equal(acc, acc_e2) and torch.equal(pot, pot_e2)
 
 
+def test_full_ensemble_in_the_benchmark_configuration(orc):
+    """The benchmark's ensemble (64 systems, 2^12..2^18 particles each, half
+    Plummer, half Hernquist), replayed from a captured graph as the benchmark
+    times it: sampled systems equal their own single-system steps bit for bit,
+    and the smallest Plummer and Hernquist systems match the oracle (counts bit
+    for bit, forces within 1e-5 at p99)."""
+    import torch
+    pos, mass, off = W.ensemble(64, 4)
+    n = int(off[-1])
+    sizes = np.diff(off)
+    print(f"[gpu] full ensemble: {n} particles in 64 systems", flush=True)
+    stream = torch.cuda.Stream()
+    ctx = gpu_context(n, max_systems=64, stream=stream)
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    acc = torch.zeros((n, 3), dtype=torch.float32, device=ctx.device)
+    pot = torch.zeros((n,), dtype=torch.float32, device=ctx.device)
+    with torch.cuda.stream(stream):
+        ctx.graph_capture(p, m, off, 0.75, acc, pot)
+        ctx.graph_launch()
+        ctx.graph_launch()
+        ctx.sync()
+    ga, gp = acc.cpu().numpy(), pot.cpu().numpy()
+    small_p = int(np.argmin(sizes[:32]))
+    small_h = 32 + int(np.argmin(sizes[32:]))
+    sample = sorted({0, 31, 32, 63, int(np.argmax(sizes)), small_p, small_h})
+    single = gpu_context(int(sizes.max()))
+    for k in sample:
+        a, b = int(off[k]), int(off[k + 1])
+        ps = torch.from_numpy(pos[a:b]).to(single.device)
+        ms = torch.from_numpy(mass[a:b]).to(single.device)
+        sa, sp = single.forces(ps, ms, 0.75)
+        single.sync()
+        np.testing.assert_array_equal(sa.cpu().numpy(), ga[a:b], err_msg=f"system {k}")
+        np.testing.assert_array_equal(sp.cpu().numpy(), gp[a:b], err_msg=f"system {k}")
+        if k in (small_p, small_h):
+            T = orc.Tree(pos[a:b], mass[a:b])
+            T.walk(0.75)
+            oa, op = T.forces()
+            npc, npp = T.counts()
+            gc = single.export("counts").cpu().numpy().view(np.uint32).astype(np.int64)
+            np.testing.assert_array_equal(gc[:, 0], npc)
+            np.testing.assert_array_equal(gc[:, 1], npp)
+            assert p99(rel_err(ga[a:b].astype(np.float64), oa)) <= TOL_P99
+            assert p99(rel_err(gp[a:b].astype(np.float64), op)) <= TOL_P99
+            print(f"[gpu] system {k} ({b - a} particles) matches the oracle", flush=True)
+
+
 def test_batch_argument_errors():
     import torch
     from paper_1204_2280_amd import mibh

@@ -152,3 +152,51 @@ def test_queue_orders_change_nothing_but_the_order():
     ratio = ws[:k].mean() / ws[-k:].mean()
     print(f"[gpu] estimator queue: mean work first tenth / last tenth = {ratio:.2f}", flush=True)
     assert ratio > 2.0
+
+def test_two_spheres_full_size():
+    """The queue-order benchmark's workload (two Plummer spheres of 2^21, the
+    benchmark's configuration): Morton and exact-count (heaviest first) orders
+    give bit-identical forces and counts, and sampled group ranges match the
+    oracle (counts bit for bit, forces within 1e-5 at p99)."""
+    torch = _torch()
+    import oracle
+    from gpu_helpers import TOL_P99, p99, rel_err
+    from paper_1204_2280_amd import mibh
+    pos, mass = W.two_plummers(1 << 21)
+    n = len(mass)
+    print(f"[gpu] two spheres, n={n}", flush=True)
+    ctx = gpu_context(n)
+    p = torch.from_numpy(pos).to(ctx.device)
+    m = torch.from_numpy(mass).to(ctx.device)
+    acc0, pot0 = ctx.forces(p, m, 0.75)
+    ctx.sync()
+    acc0, pot0 = acc0.clone(), pot0.clone()
+    c0 = ctx.export("counts").view(torch.int32).cpu().numpy().astype(np.int64)
+    ctx.set_queue_order(mibh.ORDER_EXACT, None)
+    acc1, pot1 = ctx.compute_forces(0.75)  # a second walk of the same tree: exact counts known
+    ctx.sync()
+    assert torch.equal(acc0, acc1) and torch.equal(pot0, pot1)
+    np.testing.assert_array_equal(ctx.export("counts").view(torch.int32).cpu().numpy(), c0)
+    T = oracle.Tree(pos, mass)
+    grp = T.groups()
+    ga, gp = acc0.cpu().numpy().astype(np.float64), pot0.cpu().numpy().astype(np.float64)
+    acc_g, pot_g, acc_o, pot_o = [], [], [], []
+    width = 160
+    for s0 in np.linspace(0, T.ngroups - width, 8).astype(np.int64):
+        gb, ge = int(s0), int(s0) + width
+        T.walk(0.75, groups=(gb, ge))
+        npc, npp = T.counts()
+        np.testing.assert_array_equal(c0[gb:ge, 0], npc[gb:ge])
+        np.testing.assert_array_equal(c0[gb:ge, 1], npp[gb:ge])
+        sacc, spot = T.sorted_forces()
+        f0, f1 = grp["first"][gb], grp["first"][ge - 1] + grp["count"][ge - 1]
+        idx = T.perm[f0:f1]
+        acc_o.append(sacc[f0:f1])
+        pot_o.append(spot[f0:f1])
+        acc_g.append(ga[idx])
+        pot_g.append(gp[idx])
+    ea = rel_err(np.concatenate(acc_g), np.concatenate(acc_o))
+    ep = rel_err(np.concatenate(pot_g), np.concatenate(pot_o))
+    print(f"[gpu] two spheres: {ea.size} sampled particles, acc p99 {p99(ea):.2e}, pot p99 {p99(ep):.2e}",
+          flush=True)
+    assert p99(ea) <= TOL_P99 and p99(ep) <= TOL_P99

@@ -112,6 +112,22 @@ def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 2):
         t_walk4 += time.perf_counter() - t0
     t_step4 = t_build + t_walk4 * ng / (width4 * n_ranges)
     n = len(mass)
+    # complete oracle steps at the smaller sizes (no sampling): 3 runs at 2^15, 1 at 2^20
+    from paper_1204_2280_amd import workloads
+    full = {}
+    for nn, seed, runs in ((1 << 15, 1, 3), (1 << 20, 2, 1)):
+        ps, _, ms = workloads.plummer(nn, seed, with_velocities=False)
+        best = None
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            Ts = oracle.Tree(ps, ms)
+            t1 = time.perf_counter()
+            Ts.walk(theta)
+            t2 = time.perf_counter()
+            if best is None or t2 - t0 < best[0] + best[1]:
+                best = (t1 - t0, t2 - t1)
+        full[f"plummer_n{nn}_seed{seed}"] = {"build_s": best[0], "walk_s": best[1],
+                                             "particles_per_s": nn / (best[0] + best[1]), "runs": runs}
     return {
         "value": n / t_step,
         "value_4_threads": n / t_step4,
@@ -119,6 +135,7 @@ def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 2):
         "cores": oracle.num_threads(),
         "cpu_model": cpu_model(),
         "kind": "oracle",
+        "complete_steps": full,
         "sample": (f"float64 oracle: full tree build of all {n} particles ({t_build:.2f} s, one thread) + "
                    f"walk of {sampled} of {ng} groups in {n_ranges} ranges ({t_walk:.2f} s), walk time "
                    f"scaled by {ng / sampled:.1f}; estimated step {t_step:.1f} s; with 4 threads "

@@ -51,12 +51,13 @@ __device__ __forceinline__ unsigned bitrev6(unsigned l) {
            ((l & 32u) >> 5);
 }
 
-// Exclusive prefix sum over the wave of small per-lane values (0 <= v < 16),
-// from four ballots; *total gets the wave total.
+// Exclusive prefix sum over the wave of small per-lane values (0 <= v < 2^BITS),
+// from BITS ballots; *total gets the wave total.
+template <int BITS = 4>
 __device__ __forceinline__ unsigned small_excl_scan(unsigned v, unsigned *total) {
     unsigned r = 0, t = 0;
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
+    for (int b = 0; b < BITS; b++) {
         const unsigned long long m = __ballot((v >> b) & 1u);
         r += rank_below(m) << b;
         t += (unsigned)__popcll(m) << b;
@@ -403,8 +404,22 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             npc += na;
             tot_pc += na;
 
-            // opened leaves -> particle-particle list, in rounds that fit the list
+            // opened leaves -> particle-particle list: whole leaves in one round
+            // when every leaf holds fewer than 32 particles and they fit after a
+            // flush, else in rounds of at most per_round particles per lane
             unsigned rem = leaf ? t.y : 0u, src = t.x;
+            if (__ballot(rem > 0) && !__ballot(rem > 31u)) {
+                unsigned sum;
+                const unsigned off = small_excl_scan<5>(rem, &sum);
+                if (sum + 63u <= a.pp_cap) {
+                    if (npp + sum > a.pp_cap)
+                        npp = flush_list<KAHAN, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                    for (unsigned j = 0; j < rem; j++) s_pp[npp + off + j] = src + j;
+                    npp += sum;
+                    tot_pp += sum;
+                    rem = 0;
+                }
+            }
             while (__ballot(rem > 0)) {
                 const unsigned take = min(rem, per_round);
                 unsigned sum;

@@ -93,8 +93,12 @@ __global__ __launch_bounds__(256) void k_block_active(const uint8_t *__restrict_
         active[i] = due ? 1 : 0;
         cnt += due ? 1u : 0u;
     }
+    // one atomic per block: the per-wave sums meet in LDS first
+    __shared__ unsigned long long s_part[4];
     const unsigned long long tot = wave_sum(cnt);
-    if ((threadIdx.x & 63u) == 0u) atomicAdd(nactive, tot);
+    if ((threadIdx.x & 63u) == 0u) s_part[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(nactive, (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]));
 }
 
 __global__ __launch_bounds__(256) void k_block_kick(float *__restrict__ vel, const float *__restrict__ acc,
@@ -152,11 +156,18 @@ __global__ __launch_bounds__(256) void k_rebuild_check(const uint32_t *__restric
             ref_sum += ref;
         }
     }
+    // one pair of atomics per block: the per-wave sums meet in LDS first
+    __shared__ unsigned long long s_part[2][4];
     now_sum = wave_sum(now_sum);
     ref_sum = wave_sum(ref_sum);
     if ((threadIdx.x & 63u) == 0u) {
-        atomicAdd(&sums[0], now_sum);
-        atomicAdd(&sums[1], ref_sum);
+        s_part[0][threadIdx.x >> 6] = now_sum;
+        s_part[1][threadIdx.x >> 6] = ref_sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&sums[0], (s_part[0][0] + s_part[0][1]) + (s_part[0][2] + s_part[0][3]));
+        atomicAdd(&sums[1], (s_part[1][0] + s_part[1][1]) + (s_part[1][2] + s_part[1][3]));
     }
 }
 
@@ -168,7 +179,7 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, unsi
 
 hipError_t launch_block_active(const uint8_t *level, unsigned n, unsigned tick, int R, uint8_t *active,
                                unsigned long long *nactive, hipStream_t s) {
-    const unsigned grid = min((n + 255u) / 256u, 4096u);
+    const unsigned grid = min((n + 255u) / 256u, 1024u);
     hipLaunchKernelGGL(k_block_active, dim3(grid), dim3(256), 0, s, level, n, tick, R, active, nactive);
     return hipGetLastError();
 }

@@ -39,10 +39,11 @@ __device__ __forceinline__ unsigned rank_below(unsigned long long mask) {
 }
 
 // exclusive prefix sum of small per-lane values (0 <= v < 16); *total = wave total
+template <int BITS = 4>
 __device__ __forceinline__ unsigned small_scan(unsigned v, unsigned *total) {
     unsigned r = 0, t = 0;
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
+    for (int b = 0; b < BITS; b++) {
         const unsigned long long m = __ballot((v >> b) & 1u);
         r += rank_below(m) << b;
         t += (unsigned)__popcll(m) << b;
@@ -216,9 +217,14 @@ __global__ __launch_bounds__(64, 4) void k_neighbors(NgbArgs a) {
         const unsigned obase = MODE == NGB_LISTS ? a.offset[oi] : 0u;
         const unsigned ocap = MODE == NGB_LISTS ? a.offset[oi] + a.count[oi] : 0u;
 
-        unsigned sb = 0, st = 1, gtop = 0, nl = 0;
+        // The root holds every particle, so every search opens it: its
+        // children (the root itself when it is a leaf) start the stack.
+        const uint4 tr = a.topo[root];
+        const unsigned rn = uniform(tr.w & 255u);
+        unsigned sb = 0, st = rn ? rn : 1u, gtop = 0, nl = 0;
         bool overflow = false;
-        s_stk[0] = root;
+        const unsigned first = rn ? tr.z + min(ln, rn - 1) : root;
+        if (ln < st) s_stk[ln] = first;
         __syncthreads();
         while (st != sb || gtop > 0) {
             if (st == sb) {  // refill the LDS part of the stack from the global spill
@@ -248,8 +254,25 @@ __global__ __launch_bounds__(64, 4) void k_neighbors(NgbArgs a) {
                 }
                 open = gap2 <= open2;
             }
-            // opened leaves -> candidate list, in rounds; the list is evaluated when a round does not fit
+            // opened leaves -> candidate list: whole leaves in one round when
+            // each holds fewer than 32 particles and they fit an empty list,
+            // else in rounds; the list is evaluated when a round does not fit
             unsigned rem = open && nch == 0 ? t.y : 0u, src = t.x;
+            if (__ballot(rem > 0) && !__ballot(rem > 31u)) {
+                unsigned sum;
+                const unsigned off = small_scan<5>(rem, &sum);
+                if (sum <= NGB_LIST) {
+                    if (nl + sum > NGB_LIST) {
+                        __syncthreads();
+                        ngb_eval<MODE>(a, s_list, nl, gn, p.x, p.y, p.z, pr2, hr, cnt, obase, ocap, rho);
+                        nl = 0;
+                        __syncthreads();
+                    }
+                    for (unsigned j = 0; j < rem; j++) s_list[nl + off + j] = src + j;
+                    nl += sum;
+                    rem = 0;
+                }
+            }
             while (__ballot(rem > 0)) {
                 const unsigned take = min(rem, per_round);
                 unsigned sum;

@@ -15,12 +15,13 @@
 // radius: the float32 gap can differ from the exact one by a few ulps, and the
 // margin makes the test a superset of the pairs the exact predicate admits.
 // Opened leaves put their particles on a candidate list in LDS; tiles of 64
-// candidates (one per lane) are tested against the group's particles 16 at a
-// time (positions broadcast from their lanes).  Counts go to the lane of
-// their particle by a select (no lane-dependent branch inside a loop that
-// holds cross-lane operations); list entries are placed by ballot ranks;
-// densities are summed per lane, reduced across the wave by four transposed
-// stages and two butterflies, and moved to their particle's lane.
+// candidates (one per lane) are tested against the group's particles 8 at a
+// time (positions broadcast from their lanes into scalar registers: 16 at a
+// time needed more scalar registers than a wave holds).  Counts go to the
+// lane of their particle by a select (no lane-dependent branch inside a loop
+// that holds cross-lane operations); list entries are placed by ballot ranks;
+// densities are summed per lane, reduced across the wave by three transposed
+// stages and three butterflies, and moved to their particle's lane.
 #include "mibh_device.h"
 
 namespace mibh {
@@ -29,7 +30,7 @@ namespace {
 
 constexpr unsigned NGB_LSTACK = 512;   // LDS part of the cell stack (spills to the global stack)
 constexpr unsigned NGB_LIST = 512;     // candidate list
-constexpr int NGB_CHUNK = 16;          // group particles per pass over the list
+constexpr int NGB_CHUNK = 8;          // group particles per pass over the list
 constexpr float NGB_FAR = 1.0e18f;
 
 __device__ __forceinline__ unsigned lane64() { return __lane_id(); }
@@ -56,17 +57,24 @@ __device__ __forceinline__ float readlane_f(float v, unsigned l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__device__ __forceinline__ unsigned bitrev4(unsigned x) {
-    return ((x & 1u) << 3) | ((x & 2u) << 1) | ((x & 4u) >> 1) | ((x & 8u) >> 3);
+// Bits 0..K-1 of x in reverse order.
+template <int K> __device__ __forceinline__ unsigned bitrev_k(unsigned x) {
+    unsigned r = 0;
+#pragma unroll
+    for (int b = 0; b < K; b++) r |= ((x >> b) & 1u) << (K - 1 - b);
+    return r;
 }
 
-// Sum over the wave of v[0..15]: lane l ends with the total of v[bitrev4(l >> 2)].
-__device__ __forceinline__ float reduce16(float (&v)[16]) {
+// Sum over the wave of v[0..2^K): lane l ends with the total of
+// v[bitrev_k<K>(l >> (6 - K))]; the particle of value p thus sits on the
+// lanes bitrev_k<K>(p) << (6 - K) ... + 2^(6-K) - 1.
+template <int K>
+__device__ __forceinline__ float reduce_pow2(float (&v)[1 << K]) {
     const unsigned ln = lane64();
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
+    for (int s = 0; s < K; s++) {
         const int o = 32 >> s;
-        const int len = 16 >> s;
+        const int len = (1 << K) >> s;
         const bool hi = (ln & (unsigned)o) != 0;
 #pragma unroll
         for (int p = 0; p < len / 2; p++) {
@@ -76,8 +84,8 @@ __device__ __forceinline__ float reduce16(float (&v)[16]) {
         }
     }
     float r = v[0];
-    r += __shfl_xor(r, 2, 64);
-    r += __shfl_xor(r, 1, 64);
+#pragma unroll
+    for (int o = 32 >> K; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
     return r;
 }
 
@@ -168,10 +176,11 @@ __device__ void ngb_eval(const NgbArgs &a, const uint32_t *list, unsigned nlist,
             }
         }
         if (MODE == NGB_DENSITY) {
-            const float tot = reduce16(acc);
-            // particle c0 + p sits on the lanes with bits 5..2 equal to bitrev4(p)
+            constexpr int K = NGB_CHUNK == 16 ? 4 : 3;
+            static_assert((1 << K) == NGB_CHUNK, "chunk of 8 or 16");
+            const float tot = reduce_pow2<K>(acc);
             const unsigned p = ln - c0;
-            const float mine = __shfl(tot, (int)(bitrev4(p & 15u) << 2), 64);
+            const float mine = __shfl(tot, (int)(bitrev_k<K>(p & (NGB_CHUNK - 1u)) << (6 - K)), 64);
             rho += ln >= c0 && ln < c0 + cn ? mine : 0.0f;
         }
     }

@@ -90,13 +90,14 @@ def test_refit_to_same_positions_equals_build():
     assert bool((acc0 == acc1).all()) and bool((pot0 == pot1).all())
 
 
-def test_active_walk_matches_oracle(orc):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_active_walk_matches_oracle(orc, precision):
     import torch
     pos, _, mass = W.plummer(40000, 44)
     n = len(mass)
     rng = np.random.default_rng(3)
     active = (rng.random(n) < 0.05).astype(np.uint8)
-    ctx = gpu_context(n)
+    ctx = gpu_context(n, precision=precision)
     P, M = _t(pos), _t(mass)
     ctx.build_tree(P, M)
     ctx.compute_multipoles()

@@ -53,12 +53,44 @@ struct Header {
     unsigned ncells;
     unsigned ngroups;
     unsigned lvl_begin[24]; // cells of level l are [lvl_begin[l], lvl_begin[l+1]), l = 0..20
-    // Head of the walk's group queue.  Every wave of the walk increments it, so
-    // it sits on a cache line of its own: sharing a line with the fields above,
-    // which every wave reads, made the walk 1.8 times slower.
-    alignas(256) unsigned walk_head;
-    unsigned pad[63];
+    // Heads of the walks' group queues (one per XCD, 256 bytes apart).  Every
+    // wave of a walk increments them, so they sit on cache lines of their own:
+    // sharing a line with the fields above, which every wave reads, made the
+    // walk 1.8 times slower.
+    alignas(256) unsigned walk_head[8 * 64];
 };
+
+// Group queues of the persistent walks.  gfx950 deals the workgroups of a
+// launch to its 8 XCDs in turn (workgroup i to XCD i mod 8), and each XCD has
+// its own L2.  Queue q holds the slots [q n / 8, (q + 1) n / 8) of the
+// processing order (Morton order by default), so the waves of one XCD walk
+// neighbouring groups, whose cells they then share in that XCD's L2.  A wave
+// takes slots from its XCD's queue, then from the following queues in turn as
+// each runs empty, and stops when all are empty.
+constexpr unsigned WALK_QUEUES = 8;
+constexpr unsigned QUEUE_STRIDE = 64;  // words between queue heads
+
+struct QueueCursor {
+    unsigned q, tried;  // queue in use, queues found empty
+};
+
+__device__ __forceinline__ QueueCursor queue_start() { return QueueCursor{blockIdx.x % WALK_QUEUES, 0u}; }
+
+// Next slot for the calling wave, or n when every queue is empty.  Every lane
+// calls it (lane 0 adds 1, the others 0), so no lane-dependent branch is
+// needed around it.
+__device__ __forceinline__ unsigned queue_next(unsigned *heads, unsigned n, QueueCursor &qc) {
+    while (qc.tried < WALK_QUEUES) {
+        const unsigned lo = (unsigned)((unsigned long long)n * qc.q / WALK_QUEUES);
+        const unsigned hi = (unsigned)((unsigned long long)n * (qc.q + 1u) / WALK_QUEUES);
+        const unsigned s = __builtin_amdgcn_readfirstlane(
+            atomicAdd(heads + QUEUE_STRIDE * qc.q, __lane_id() == 0 ? 1u : 0u));
+        if (s < hi - lo) return lo + s;
+        qc.tried++;
+        qc.q = (qc.q + 1u) % WALK_QUEUES;
+    }
+    return n;
+}
 
 // Walk queue order by predicted or measured work: quarter-octave buckets of
 // log2(work), heaviest first, Morton order within a bucket.

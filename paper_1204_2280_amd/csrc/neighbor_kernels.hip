@@ -8,7 +8,7 @@
 //   * rho_i = sum over the neighbours within r_i = 2 h_i of m_j W(|d|, h_i),
 //     W the cubic spline of Monaghan & Lattanzio (1985).
 //
-// One wave64 per group, persistent waves on the walk's queue head.  The
+// One wave64 per group, persistent waves on the walk's per-XCD group queues.  The
 // traversal opens a cell when the gap between the group's bounding box and
 // the cell's particle box (both float32, from the multipole pass) is within
 // the group's largest radius, with a relative margin of 1e-5 on the squared
@@ -196,9 +196,10 @@ __global__ __launch_bounds__(64, 4) void k_neighbors(NgbArgs a) {
     if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
     constexpr unsigned per_round = NGB_LIST >> 6;  // 8 particles per lane: a round always fits an empty list
     const unsigned ngroups = uniform(a.hdr->ngroups);
+    QueueCursor qc = queue_start();
     for (;;) {
         // every lane takes part in the queue atomic (see the walk's queue loop)
-        const unsigned g = uniform(atomicAdd(a.head, ln == 0 ? 1u : 0u));
+        const unsigned g = queue_next(a.head, ngroups, qc);
         if (g >= ngroups) break;
         const uint2 gr = a.groups[g];
         const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u);
@@ -402,7 +403,7 @@ hipError_t launch_neighbors(const Buffers &b, int mode, const float *radius, uin
                             uint32_t *index, float *rho, unsigned nsys, hipStream_t s) {
     NgbArgs a;
     a.hdr = b.hdr;
-    a.head = &b.hdr->walk_head;
+    a.head = b.hdr->walk_head;
     a.topo = b.topo;
     a.cbox = b.cbox;
     a.spos = b.spos;
@@ -415,7 +416,7 @@ hipError_t launch_neighbors(const Buffers &b, int mode, const float *radius, uin
     a.offset = offset;
     a.index = index;
     a.rho = rho;
-    hipError_t e = launch_fill_u32(&b.hdr->walk_head, 1u, 0u, s);
+    hipError_t e = launch_fill_u32(b.hdr->walk_head, WALK_QUEUES * QUEUE_STRIDE, 0u, s);
     if (e != hipSuccess) return e;
     if (mode == NGB_COUNT)
         hipLaunchKernelGGL(k_neighbors<NGB_COUNT>, dim3(b.walk_waves), dim3(64), 0, s, a);

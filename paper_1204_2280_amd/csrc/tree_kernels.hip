@@ -237,9 +237,9 @@ __global__ void k_header_reset(unsigned n, unsigned nsys, Header *__restrict__ h
         hdr->n = n;
         hdr->ncells = 0;
         hdr->ngroups = 0;
-        hdr->walk_head = 0;
         for (int l = 0; l < 24; l++) hdr->lvl_begin[l] = 0;
     }
+    if (threadIdx.x < WALK_QUEUES) hdr->walk_head[QUEUE_STRIDE * threadIdx.x] = 0;
 }
 
 hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
@@ -773,37 +773,72 @@ hipError_t launch_build(const Buffers &b, unsigned n, unsigned nsys, int ncrit, 
 
 constexpr unsigned LEAF_REGS = 16;  // leaves up to this size are summed from registers
 
-// lev < 0: every leaf; otherwise the internal cells of level lev.
-__global__ __launch_bounds__(256) void k_multipole_level(
-    int lev_in, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
+// Side and geometric centre of cell t (level from its record, corner from the
+// key prefix of its first particle).
+__device__ __forceinline__ double cell_geometry(const uint4 &t, const SysCube *__restrict__ cube,
+                                                const uint64_t *__restrict__ keys, double centre[3]) {
+#pragma clang fp contract(off)
+    const int lev = (int)((t.w >> 8) & 255u);
+    const SysCube cb3 = cube[t.w >> 16];
+    const double lo[3] = {(double)cb3.lo[0], (double)cb3.lo[1], (double)cb3.lo[2]};
+    const double l = ldexp(1.0, cb3.k - lev);
+    const uint64_t pre = keys[t.x] >> (3 * (KEY_LEVELS - lev));
+    const double q[3] = {(double)compact3(pre >> 2), (double)compact3(pre >> 1), (double)compact3(pre)};
+    for (int a = 0; a < 3; a++) {
+        const double corner = lo[a] + q[a] * l;
+        centre[a] = corner + 0.5 * l;
+    }
+    return l;
+}
+
+// Writes cell c's moments and the quantities derived from them.
+__device__ __forceinline__ void store_cell(unsigned c, double l, const double centre[3], double M,
+                                           const double com[3], const double S[6], const float bn[3],
+                                           const float bx[3], double *__restrict__ mp, double *__restrict__ delta,
+                                           float *__restrict__ cbox, double *__restrict__ lside,
+                                           float4 *__restrict__ cmac, float4 *__restrict__ ceval) {
+#pragma clang fp contract(off)
+    double *o = mp + 10 * (size_t)c;
+    o[0] = M;
+    o[1] = com[0];
+    o[2] = com[1];
+    o[3] = com[2];
+    for (int s = 0; s < 6; s++) o[4 + s] = S[s];
+    const double tr = (S[0] + S[1]) + S[2];
+    const double Q0 = 3.0 * S[0] - tr, Q1 = 3.0 * S[1] - tr, Q2 = 3.0 * S[2] - tr;
+    const double dx = com[0] - centre[0], dy = com[1] - centre[1], dz = com[2] - centre[2];
+    delta[c] = sqrt((dx * dx + dy * dy) + dz * dz);
+    double reach = 0.0;
+    for (int a = 0; a < 3; a++) {
+        reach = fmax(reach, centre[a] - (double)bn[a]);
+        reach = fmax(reach, (double)bx[a] - centre[a]);
+        cbox[6 * (size_t)c + a] = bn[a];
+        cbox[6 * (size_t)c + 3 + a] = bx[a];
+    }
+    lside[c] = fmax(l, 2.0 * reach);
+    cmac[c] = make_float4((float)com[0], (float)com[1], (float)com[2], 0.0f);
+    ceval[2 * (size_t)c] = make_float4((float)M, (float)Q0, (float)Q1, (float)Q2);
+    ceval[2 * (size_t)c + 1] = make_float4((float)(3.0 * S[3]), (float)(3.0 * S[4]), (float)(3.0 * S[5]), 0.0f);
+}
+
+// Every leaf of every level.
+__global__ __launch_bounds__(256) void k_multipole_leaves(
+    const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
     const float4 *__restrict__ spos, const uint64_t *__restrict__ keys, double *__restrict__ mp,
     double *__restrict__ delta, float *__restrict__ cbox, double *__restrict__ lside, float4 *__restrict__ cmac,
     float4 *__restrict__ ceval, unsigned cap_cells) {
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
-    const bool leaves = lev_in < 0;
-    const unsigned cb = leaves ? 0u : min(hdr->lvl_begin[lev_in], nc);
-    const unsigned ce = leaves ? nc : min(hdr->lvl_begin[lev_in + 1], nc);
-    for (unsigned c = cb + blockIdx.x * 256u + threadIdx.x; c < ce; c += gridDim.x * 256u) {
+    for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
         const uint4 t = topo[c];
-        const unsigned nch = t.w & 255u;
-        if ((nch == 0) != leaves) continue;
-        const int lev = (int)((t.w >> 8) & 255u);
-        const SysCube cb3 = cube[t.w >> 16];
-        const double lo[3] = {(double)cb3.lo[0], (double)cb3.lo[1], (double)cb3.lo[2]};
-        const double l = ldexp(1.0, cb3.k - lev);
-        const uint64_t pre = keys[t.x] >> (3 * (KEY_LEVELS - lev));
-        const double q[3] = {(double)compact3(pre >> 2), (double)compact3(pre >> 1), (double)compact3(pre)};
+        if ((t.w & 255u) != 0) continue;
         double centre[3];
-        for (int a = 0; a < 3; a++) {
-            const double corner = lo[a] + q[a] * l;
-            centre[a] = corner + 0.5 * l;
-        }
+        const double l = cell_geometry(t, cube, keys, centre);
         double M = 0.0, cm[3] = {0.0, 0.0, 0.0}, com[3];
         double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         float bn[3], bx[3];
-        if (nch == 0 && t.y <= LEAF_REGS) {
+        if (t.y <= LEAF_REGS) {
             // a leaf of up to LEAF_REGS particles: all loads in flight at once,
             // both passes from registers (same operations in the same order)
             float4 pr[LEAF_REGS];
@@ -849,7 +884,7 @@ __global__ __launch_bounds__(256) void k_multipole_level(
                     S[5] = fma(m * dy, dz, S[5]);
                 }
             }
-        } else if (nch == 0) {
+        } else {
             {
                 const float4 p0 = spos[t.x];
                 bn[0] = bx[0] = p0.x;
@@ -882,71 +917,93 @@ __global__ __launch_bounds__(256) void k_multipole_level(
                 S[4] = fma(m * dx, dz, S[4]);
                 S[5] = fma(m * dy, dz, S[5]);
             }
-        } else {
-            for (int a = 0; a < 3; a++) {
-                bn[a] = cbox[6 * (size_t)t.z + a];
-                bx[a] = cbox[6 * (size_t)t.z + 3 + a];
-            }
-            for (unsigned ch = t.z + 1; ch < t.z + nch; ch++) {
-                for (int a = 0; a < 3; a++) {
-                    bn[a] = fminf(bn[a], cbox[6 * (size_t)ch + a]);
-                    bx[a] = fmaxf(bx[a], cbox[6 * (size_t)ch + 3 + a]);
-                }
-            }
-            for (unsigned ch = t.z; ch < t.z + nch; ch++) {
-                const double *p = mp + 10 * (size_t)ch;
-                M = M + p[0];
-                cm[0] = fma(p[0], p[1], cm[0]);
-                cm[1] = fma(p[0], p[2], cm[1]);
-                cm[2] = fma(p[0], p[3], cm[2]);
-            }
-            for (int a = 0; a < 3; a++) com[a] = M > 0.0 ? cm[a] / M : centre[a];
-            for (unsigned ch = t.z; ch < t.z + nch; ch++) {
-                const double *p = mp + 10 * (size_t)ch;
-                const double ex = p[1] - com[0], ey = p[2] - com[1], ez = p[3] - com[2];
-                const double Mc = p[0];
-                S[0] = S[0] + (p[4] + (Mc * ex) * ex);
-                S[1] = S[1] + (p[5] + (Mc * ey) * ey);
-                S[2] = S[2] + (p[6] + (Mc * ez) * ez);
-                S[3] = S[3] + (p[7] + (Mc * ex) * ey);
-                S[4] = S[4] + (p[8] + (Mc * ex) * ez);
-                S[5] = S[5] + (p[9] + (Mc * ey) * ez);
+        }
+        store_cell(c, l, centre, M, com, S, bn, bx, mp, delta, cbox, lside, cmac, ceval);
+    }
+}
+
+// The internal cells of level lev (their children, at level lev + 1, are
+// done).  The up to 8 children's moments and boxes are loaded together, one
+// round trip per cell instead of one per child, then combined in child order.
+__global__ __launch_bounds__(256) void k_multipole_internal(
+    int lev, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
+    const uint64_t *__restrict__ keys, double *__restrict__ mp, double *__restrict__ delta,
+    float *__restrict__ cbox, double *__restrict__ lside, float4 *__restrict__ cmac, float4 *__restrict__ ceval,
+    unsigned cap_cells) {
+#pragma clang fp contract(off)
+    if (hdr->flags & FLAG_CELLCAP) return;
+    const unsigned nc = min(hdr->ncells, cap_cells);
+    const unsigned cb = min(hdr->lvl_begin[lev], nc), ce = min(hdr->lvl_begin[lev + 1], nc);
+    for (unsigned c = cb + blockIdx.x * 256u + threadIdx.x; c < ce; c += gridDim.x * 256u) {
+        const uint4 t = topo[c];
+        const unsigned nch = t.w & 255u;
+        if (nch == 0) continue;
+        double2 cm2[8][5];  // child moments: M, com xyz, S xx yy zz xy xz yz
+        float2 cb2[8][3];   // child boxes: min xyz, max xyz
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if ((unsigned)j < nch) {
+                const double2 *pm = reinterpret_cast<const double2 *>(mp + 10 * (size_t)(t.z + j));
+                const float2 *pb = reinterpret_cast<const float2 *>(cbox + 6 * (size_t)(t.z + j));
+#pragma unroll
+                for (int a = 0; a < 5; a++) cm2[j][a] = pm[a];
+#pragma unroll
+                for (int a = 0; a < 3; a++) cb2[j][a] = pb[a];
             }
         }
-        double *o = mp + 10 * (size_t)c;
-        o[0] = M;
-        o[1] = com[0];
-        o[2] = com[1];
-        o[3] = com[2];
-        for (int s = 0; s < 6; s++) o[4 + s] = S[s];
-        const double tr = (S[0] + S[1]) + S[2];
-        const double Q0 = 3.0 * S[0] - tr, Q1 = 3.0 * S[1] - tr, Q2 = 3.0 * S[2] - tr;
-        const double dx = com[0] - centre[0], dy = com[1] - centre[1], dz = com[2] - centre[2];
-        delta[c] = sqrt((dx * dx + dy * dy) + dz * dz);
-        double reach = 0.0;
-        for (int a = 0; a < 3; a++) {
-            reach = fmax(reach, centre[a] - (double)bn[a]);
-            reach = fmax(reach, (double)bx[a] - centre[a]);
-            cbox[6 * (size_t)c + a] = bn[a];
-            cbox[6 * (size_t)c + 3 + a] = bx[a];
+        double centre[3];
+        const double l = cell_geometry(t, cube, keys, centre);
+        float bn[3] = {cb2[0][0].x, cb2[0][0].y, cb2[0][1].x}, bx[3] = {cb2[0][1].y, cb2[0][2].x, cb2[0][2].y};
+#pragma unroll
+        for (int j = 1; j < 8; j++) {
+            if ((unsigned)j < nch) {
+                bn[0] = fminf(bn[0], cb2[j][0].x);
+                bn[1] = fminf(bn[1], cb2[j][0].y);
+                bn[2] = fminf(bn[2], cb2[j][1].x);
+                bx[0] = fmaxf(bx[0], cb2[j][1].y);
+                bx[1] = fmaxf(bx[1], cb2[j][2].x);
+                bx[2] = fmaxf(bx[2], cb2[j][2].y);
+            }
         }
-        lside[c] = fmax(l, 2.0 * reach);
-        cmac[c] = make_float4((float)com[0], (float)com[1], (float)com[2], 0.0f);
-        ceval[2 * (size_t)c] = make_float4((float)M, (float)Q0, (float)Q1, (float)Q2);
-        ceval[2 * (size_t)c + 1] =
-            make_float4((float)(3.0 * S[3]), (float)(3.0 * S[4]), (float)(3.0 * S[5]), 0.0f);
+        double M = 0.0, cm[3] = {0.0, 0.0, 0.0}, com[3];
+        double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if ((unsigned)j < nch) {
+                const double Mc = cm2[j][0].x;
+                M = M + Mc;
+                cm[0] = fma(Mc, cm2[j][0].y, cm[0]);
+                cm[1] = fma(Mc, cm2[j][1].x, cm[1]);
+                cm[2] = fma(Mc, cm2[j][1].y, cm[2]);
+            }
+        }
+        for (int a = 0; a < 3; a++) com[a] = M > 0.0 ? cm[a] / M : centre[a];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if ((unsigned)j < nch) {
+                const double Mc = cm2[j][0].x;
+                const double ex = cm2[j][0].y - com[0], ey = cm2[j][1].x - com[1], ez = cm2[j][1].y - com[2];
+                S[0] = S[0] + (cm2[j][2].x + (Mc * ex) * ex);
+                S[1] = S[1] + (cm2[j][2].y + (Mc * ey) * ey);
+                S[2] = S[2] + (cm2[j][3].x + (Mc * ez) * ez);
+                S[3] = S[3] + (cm2[j][3].y + (Mc * ex) * ey);
+                S[4] = S[4] + (cm2[j][4].x + (Mc * ex) * ez);
+                S[5] = S[5] + (cm2[j][4].y + (Mc * ey) * ez);
+            }
+        }
+        store_cell(c, l, centre, M, com, S, bn, bx, mp, delta, cbox, lside, cmac, ceval);
     }
 }
 
 hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s) {
+    const uint64_t *keys = b.keys[sorted_buffer(nsys)];
     const unsigned grid = min((b.cap_cells + 255u) / 256u, 2048u);
-    auto level = [&](int lev) {
-        hipLaunchKernelGGL(k_multipole_level, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.cube, b.topo, b.spos,
-                           b.keys[sorted_buffer(nsys)], b.mp, b.delta, b.cbox, b.lside, b.cmac, b.ceval,
-                           b.cap_cells);
-    };
-    level(-1);  // every leaf
-    for (int lev = KEY_LEVELS - 1; lev >= 0; lev--) level(lev);  // level KEY_LEVELS holds leaves only
+    hipLaunchKernelGGL(k_multipole_leaves, dim3(grid), dim3(256), 0, s, b.hdr, b.cube, b.topo, b.spos, keys, b.mp,
+                       b.delta, b.cbox, b.lside, b.cmac, b.ceval, b.cap_cells);
+    // level KEY_LEVELS holds leaves only
+    for (int lev = KEY_LEVELS - 1; lev >= 0; lev--)
+        hipLaunchKernelGGL(k_multipole_internal, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.cube, b.topo, keys,
+                           b.mp, b.delta, b.cbox, b.lside, b.cmac, b.ceval, b.cap_cells);
     return hipGetLastError();
 }
 
@@ -959,7 +1016,8 @@ __global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr, cons
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
-    if (blockIdx.x == 0 && threadIdx.x == 0) hdr->walk_head = 0;  // queue of the walk that follows
+    if (blockIdx.x == 0 && threadIdx.x < WALK_QUEUES)
+        hdr->walk_head[QUEUE_STRIDE * threadIdx.x] = 0;  // queues of the walk that follows
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
         const double ro = lside[c] / theta + delta[c];
         cmac[c].w = (float)(ro * ro);

@@ -3,11 +3,11 @@
 //
 // One wave64 per group (the vector-machine idea of Barnes 1990: one
 // interaction list shared by a group of nearby particles), persistent waves
-// pulling groups from one device-wide queue: an atomic head on a cache line of
-// its own, over the groups in Morton order (concurrent waves then walk
-// spatial neighbours, whose cells are shared in L2) or over a work-ordered
-// permutation, heaviest groups first (longest-processing-time order, which
-// shortens the tail of the persistent grid).
+// pulling groups from eight queues, one per XCD, each an atomic head on a
+// cache line of its own over one eighth of the processing order: the groups
+// in Morton order (the waves of an XCD then walk spatial neighbours, whose
+// cells they share in that XCD's L2) or a work-ordered permutation, heaviest
+// groups first.  A wave whose queue is empty takes groups from the others.
 //
 // Traversal: lanes hold up to 64 candidate cells popped from a per-wave stack
 // kept in LDS (circular, spilling its bottom to a per-wave global stack when
@@ -317,12 +317,13 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
     static_assert(WALK_PP_LDS <= 1024, "per-round counts must fit the 4-bit prefix sums");
     const unsigned ngroups = a.qlen ? uniform(*a.qlen) : uniform(a.hdr->ngroups);
     const unsigned pc_cap = min(a.pc_cap, PC_LDS);
+    QueueCursor qc = queue_start();
     for (;;) {
         // Every lane executes the queue atomic (only lane 0 adds 1) so that no
         // lane-dependent branch sits inside this loop: the compiler may split a
         // loop on a loop-invariant divergent condition, which would separate
         // lane 0 from the cross-lane operations of the other lanes.
-        const unsigned slot = uniform(atomicAdd(a.head, ln == 0 ? 1u : 0u));
+        const unsigned slot = queue_next(a.head, ngroups, qc);
         if (slot >= ngroups) break;
         const unsigned g = a.order ? uniform(a.order[slot]) : slot;
         const uint2 gr = a.groups[g];
@@ -504,7 +505,7 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
     a.order = order;
     a.qlen = qlen;
     a.active = active;
-    a.head = &b.hdr->walk_head;
+    a.head = b.hdr->walk_head;
     a.acc = acc;
     a.pot = pot;
     a.eps2 = eps2;

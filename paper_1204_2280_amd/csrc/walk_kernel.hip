@@ -143,7 +143,7 @@ struct WalkArgs {
     const uint32_t *order;   // queue order (NULL: Morton order)
     const uint32_t *qlen;    // number of queue entries to walk (NULL: all groups)
     const uint8_t *active;   // per input particle, nonzero = evaluate it (NULL: every particle)
-    unsigned *head;          // queue head
+    unsigned *head;          // heads of the group queues (one per XCD)
     float *acc, *pot;
     float eps2, G;
     unsigned pc_cap, pp_cap;

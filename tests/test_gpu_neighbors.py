@@ -59,6 +59,24 @@ def test_counts_and_lists_match_oracle(orc, case):
         np.testing.assert_array_equal(np.sort(idx[off[i]:off[i + 1]]), ref[i])
 
 
+def test_few_waves_drain_every_queue(orc):
+    """Neighbour search on a grid of 3 persistent waves (fewer than the 8 per-XCD group queues):
+    the same counts and lists as the oracle."""
+    from oracle import neighbors as nb
+    name, pos, mass, r = next(c for c in _cases() if c[0] == "random")
+    ctx = gpu_context(len(mass), walk_waves=3)
+    ctx.build_tree(_t(pos), _t(mass))
+    ctx.compute_multipoles()
+    R = _t(r)
+    cnt = ctx.neighbor_count(R).cpu().numpy().astype(np.int64)
+    ref = nb.neighbor_lists(pos, r)
+    np.testing.assert_array_equal(cnt, [len(x) for x in ref])
+    c2, off, idx = ctx.neighbor_list(R)
+    off, idx = off.cpu().numpy().astype(np.int64), idx.cpu().numpy()
+    for i in range(len(mass)):
+        np.testing.assert_array_equal(np.sort(idx[off[i]:off[i + 1]]), ref[i])
+
+
 def test_list_capacity_overflow():
     from paper_1204_2280_amd import mibh
     pos, _, mass = W.plummer(2000, 23, with_velocities=False)

@@ -129,6 +129,21 @@ def test_small_list_capacities_force_flushes(orc):
     assert p99(rel_err(g["acc"], acc)) <= TOL_P99 and p99(rel_err(g["pot"], pot)) <= TOL_P99
 
 
+@pytest.mark.parametrize("waves", [1, 3, 8, 13])
+def test_few_walk_waves_drain_every_queue(waves):
+    """The walk's groups sit in one queue per XCD (workgroup i serves queue i mod 8 first, then
+    takes groups from the others).  With fewer persistent waves than queues, some queues have no
+    waves of their own; every group must still be walked once, with results bitwise equal to the
+    default grid's (each group's lists and sums do not depend on the wave that walks it)."""
+    pos, mass = _case("plummer_5003")
+    print(f"[gpu] walk with {waves} persistent waves", flush=True)
+    ref = run_gpu(gpu_context(6000), pos, mass, 0.75, exports=("counts",))
+    g = run_gpu(gpu_context(6000, walk_waves=waves), pos, mass, 0.75, exports=("counts",))
+    np.testing.assert_array_equal(g["counts"], ref["counts"])
+    np.testing.assert_array_equal(g["acc"], ref["acc"])
+    np.testing.assert_array_equal(g["pot"], ref["pot"])
+
+
 @pytest.mark.parametrize("ncrit,gcap", [(8, 32), (1, 1), (32, 64), (16, 16)])
 def test_other_leaf_and_group_sizes(orc, ncrit, gcap):
     pos, mass = _case("hernquist_9000")

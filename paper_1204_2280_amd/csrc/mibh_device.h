@@ -16,7 +16,7 @@ constexpr int SORT_THREADS = 256;       // 4 waves
 constexpr int SORT_ITEMS = 16;          // keys per thread per tile
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
 
-constexpr int BUILD_THREADS = 256;      // particles per build block
+constexpr int BUILD_THREADS = 1024;     // particles per build block
 constexpr int MAX_WINDOW = 64;          // largest group_cap (halo of the build window)
 constexpr int BBOX_BLOCKS = 1024;
 constexpr int ENERGY_BLOCKS = 1024;

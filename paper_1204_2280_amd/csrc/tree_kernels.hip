@@ -636,6 +636,8 @@ __global__ __launch_bounds__(1024) void k_build_scan(uint32_t *__restrict__ blkc
     if (threadIdx.x == 0) ctot[blockIdx.x] = total;
 }
 
+constexpr unsigned BUILD_PENDING = 512;  // cell ends searched at the end of a block (beyond: inline)
+
 __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
     const uchar4 *__restrict__ lvinfo, const uint64_t *__restrict__ keys, unsigned n, unsigned nsys,
     const uint32_t *__restrict__ sys_off, int gcap, const uint32_t *__restrict__ blkcnt,
@@ -645,6 +647,12 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
     __shared__ uint32_t s_base[NCOUNTERS];   // first cell number of each level; 0 for groups
     __shared__ uint32_t s_blk[NCOUNTERS];    // this block's offset within each level
     __shared__ uint32_t s_wpre[NW][NCOUNTERS];
+    // cells whose end lies beyond their wave: record (cell, first, child_first,
+    // system | level word) and (system end, group + 1 or 0), searched at the end
+    __shared__ uint4 s_prec[BUILD_PENDING];
+    __shared__ uint2 s_pext[BUILD_PENDING];
+    __shared__ unsigned s_np;
+    if (threadIdx.x == 0) s_np = 0;
     if (threadIdx.x == 0) {
         uint32_t run = 0;
         for (int l = 0; l <= KEY_LEVELS; l++) {
@@ -690,9 +698,13 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
     // A level-l cell starting at i ends at the first j > i with cl(j) < l (or
     // where the particles end): the wave finds it from a ballot of those
     // boundaries when it lies inside the wave, else by searching the keys.
+    // Ends found by searching the keys are deferred to the end of the kernel,
+    // where the block's threads take one search each: a particle that starts
+    // large cells at many levels (the first particles of the big cells) would
+    // otherwise run its searches one after the other, the kernel's longest path.
     const int ci = clo - 1;
     const unsigned ln = lane64();
-    unsigned next = 0, gend = 0;
+    unsigned next = 0, gend = 0, gpend = 0;
     for (int l = KEY_LEVELS; l >= 0; l--) {
         const bool pred = clo <= l && l <= leaf;
         const unsigned long long b = __ballot(pred);
@@ -701,22 +713,43 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
         if (pred) {
             const unsigned idx = s_base[l] + s_blk[l] + s_wpre[w][l] + rank_below(b);
             const unsigned long long after = ln < 63 ? bnd >> (ln + 1) : 0ull;
-            const unsigned end = after ? i + (unsigned)__ffsll((long long)after) : run_end(keys, send, i, l);
             const unsigned cf = l < leaf ? next : 0u;
-            if (idx < cap_cells) topo[idx] = make_uint4(i, end - i, cf, (sys << 16) | ((unsigned)l << 8));
+            const unsigned word = (sys << 16) | ((unsigned)l << 8);
+            const unsigned k = after ? BUILD_PENDING : atomicAdd(&s_np, 1u);
+            if (k < BUILD_PENDING) {
+                s_prec[k] = make_uint4(idx, i, cf, word);
+                s_pext[k] = make_uint2(send, 0u);
+                if (l == glev) gpend = k + 1;
+            } else {  // end inside the wave, or no room left to defer
+                const unsigned end = after ? i + (unsigned)__ffsll((long long)after) : run_end(keys, send, i, l);
+                if (idx < cap_cells) topo[idx] = make_uint4(i, end - i, cf, word);
+                if (l == glev) gend = end;
+            }
             next = idx;
-            if (l == glev) gend = end;
         }
     }
     {
         const unsigned long long b = __ballot(gstart);
         if (gstart) {
             const unsigned g = s_blk[NCOUNTERS - 1] + s_wpre[w][NCOUNTERS - 1] + rank_below(b);
-            unsigned cnt;
-            if (info.w & 2) cnt = min((unsigned)gcap, run_end(keys, send, i, KEY_LEVELS) - i);
-            else cnt = (gend ? gend : run_end(keys, send, i, glev)) - i;
-            groups[g] = make_uint2(i, (sys << 16) | ((unsigned)glev << 8) | cnt);
+            const unsigned gword = (sys << 16) | ((unsigned)glev << 8);
+            if (info.w & 2) {
+                groups[g] = make_uint2(i, gword | min((unsigned)gcap, run_end(keys, send, i, KEY_LEVELS) - i));
+            } else if (gend == 0 && gpend) {
+                s_pext[gpend - 1].y = g + 1;  // written with its cell's end below
+            } else {
+                groups[g] = make_uint2(i, gword | ((gend ? gend : run_end(keys, send, i, glev)) - i));
+            }
         }
+    }
+    __syncthreads();
+    const unsigned np = min(s_np, BUILD_PENDING);
+    for (unsigned k = threadIdx.x; k < np; k += BUILD_THREADS) {
+        const uint4 r = s_prec[k];
+        const uint2 e = s_pext[k];
+        const unsigned end = run_end(keys, e.x, r.y, (int)((r.w >> 8) & 255u));
+        if (r.x < cap_cells) topo[r.x] = make_uint4(r.y, end - r.y, r.z, r.w);
+        if (e.y) groups[e.y - 1] = make_uint2(r.y, r.w | (end - r.y));
     }
 }
 
@@ -925,7 +958,12 @@ __global__ __launch_bounds__(256) void k_multipole_leaves(
 // The internal cells of level lev (their children, at level lev + 1, are
 // done).  The up to 8 children's moments and boxes are loaded together, one
 // round trip per cell instead of one per child, then combined in child order.
-__global__ __launch_bounds__(256) void k_multipole_internal(
+// One wave per workgroup: about one cell in five of a level is internal, and
+// the cell code holds many registers (two waves per SIMD), so small
+// workgroups spread a level's internal cells over more compute units.
+constexpr unsigned MP_INTERNAL_THREADS = 64;
+
+__global__ __launch_bounds__(MP_INTERNAL_THREADS) void k_multipole_internal(
     int lev, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
     const uint64_t *__restrict__ keys, double *__restrict__ mp, double *__restrict__ delta,
     float *__restrict__ cbox, double *__restrict__ lside, float4 *__restrict__ cmac, float4 *__restrict__ ceval,
@@ -934,7 +972,8 @@ __global__ __launch_bounds__(256) void k_multipole_internal(
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
     const unsigned cb = min(hdr->lvl_begin[lev], nc), ce = min(hdr->lvl_begin[lev + 1], nc);
-    for (unsigned c = cb + blockIdx.x * 256u + threadIdx.x; c < ce; c += gridDim.x * 256u) {
+    for (unsigned c = cb + blockIdx.x * MP_INTERNAL_THREADS + threadIdx.x; c < ce;
+         c += gridDim.x * MP_INTERNAL_THREADS) {
         const uint4 t = topo[c];
         const unsigned nch = t.w & 255u;
         if (nch == 0) continue;
@@ -1001,9 +1040,10 @@ hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_multipole_leaves, dim3(grid), dim3(256), 0, s, b.hdr, b.cube, b.topo, b.spos, keys, b.mp,
                        b.delta, b.cbox, b.lside, b.cmac, b.ceval, b.cap_cells);
     // level KEY_LEVELS holds leaves only
+    const unsigned igrid = min((b.cap_cells + MP_INTERNAL_THREADS - 1u) / MP_INTERNAL_THREADS, 8192u);
     for (int lev = KEY_LEVELS - 1; lev >= 0; lev--)
-        hipLaunchKernelGGL(k_multipole_internal, dim3(grid), dim3(256), 0, s, lev, b.hdr, b.cube, b.topo, keys,
-                           b.mp, b.delta, b.cbox, b.lside, b.cmac, b.ceval, b.cap_cells);
+        hipLaunchKernelGGL(k_multipole_internal, dim3(igrid), dim3(MP_INTERNAL_THREADS), 0, s, lev, b.hdr, b.cube,
+                           b.topo, keys, b.mp, b.delta, b.cbox, b.lside, b.cmac, b.ceval, b.cap_cells);
     return hipGetLastError();
 }
 

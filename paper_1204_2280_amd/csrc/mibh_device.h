@@ -13,7 +13,7 @@ constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SORT_PASSES = 8;          // 64 bits in 8-bit digits (bits 60..63 are zero)
 constexpr int SORT_THREADS = 256;       // 4 waves
-constexpr int SORT_ITEMS = 16;          // keys per thread per tile
+constexpr int SORT_ITEMS = 8;           // keys per thread per tile (16 and 4 were slower)
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
 
 constexpr int BUILD_THREADS = 1024;     // particles per build block

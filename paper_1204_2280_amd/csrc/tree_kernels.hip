@@ -903,6 +903,11 @@ __global__ __launch_bounds__(256) void k_multipole_leaves(
                 }
             }
             for (int a = 0; a < 3; a++) com[a] = M > 0.0 ? cm[a] / M : centre[a];
+            // the second pass converts the particles to float64 again instead of
+            // keeping 16 x 4 float64 values live across the divisions (128 registers)
+#pragma unroll
+            for (int j = 0; j < LEAF_REGS; j++)
+                asm volatile("" : "+v"(pr[j].x), "+v"(pr[j].y), "+v"(pr[j].z), "+v"(pr[j].w));
 #pragma unroll
             for (int j = 0; j < LEAF_REGS; j++) {
                 if ((unsigned)j < t.y) {

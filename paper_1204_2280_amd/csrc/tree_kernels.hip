@@ -636,7 +636,12 @@ __global__ __launch_bounds__(1024) void k_build_scan(uint32_t *__restrict__ blkc
     if (threadIdx.x == 0) ctot[blockIdx.x] = total;
 }
 
-constexpr unsigned BUILD_PENDING = 512;  // cell ends searched at the end of a block (beyond: inline)
+// Cell ends searched at the end of a block.  A cell whose end lies beyond its
+// first particle's wave contains that wave's last particle, so a wave defers at
+// most one cell per level: 16 waves x 21 levels fit (the inline search below
+// is only a guard).
+constexpr unsigned BUILD_PENDING = 512;
+static_assert(BUILD_PENDING >= (BUILD_THREADS / 64) * (KEY_LEVELS + 1), "one deferred cell per wave and level");
 
 __global__ __launch_bounds__(BUILD_THREADS) void k_build_write(
     const uchar4 *__restrict__ lvinfo, const uint64_t *__restrict__ keys, unsigned n, unsigned nsys,

@@ -35,13 +35,45 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=all"]
+
+
+def build_sanitized() -> str:
+    """Compile bh_oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer
+    into liboracle_san.so (same arithmetic flags as the normal build, one
+    thread team per OpenMP region as before).  Load it through MIBH_ORACLE_SO
+    with the ASan runtime preloaded; see ``sanitizer_env``."""
+    flags = [f for f in GCC_FLAGS if f != "-O2"] + SAN_FLAGS
+    tmp = SAN_LIB + ".tmp"
+    subprocess.run(["gcc", *flags, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
+def sanitizer_env(base=None) -> dict:
+    """Environment for a child Python process that runs the oracle from the
+    sanitizer build: the ASan runtime preloaded (it must come first), leak
+    checks off (the interpreter keeps its allocations until exit), any report
+    fatal."""
+    env = dict(os.environ if base is None else base)
+    asan = subprocess.run(["gcc", "-print-file-name=libasan.so"], check=True, capture_output=True,
+                          text=True).stdout.strip()
+    env["LD_PRELOAD"] = asan
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:halt_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    env["MIBH_ORACLE_SO"] = SAN_LIB
+    return env
+
+
 _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        alt = os.environ.get("MIBH_ORACLE_SO")  # a deliberately altered oracle, for mutation checks
+        alt = os.environ.get("MIBH_ORACLE_SO")  # an altered build: mutation checks, sanitizers
         if not alt:
             build()
         L = C.CDLL(alt or _LIB)

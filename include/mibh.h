@@ -203,7 +203,10 @@ mibh_status mibh_energy(mibh_ctx *ctx, const float *d_vel, double *T, double *W)
  * [n][3], [n] receive the forces of the final positions.  With
  * log_every > 0, h_log (host, log_cap >= nsteps/log_every + 1 rows) gets
  * rows (t, T, W) in float64 (mibh_energy) at step 0 and every log_every
- * steps, *nlog the number of rows; each row synchronises.  Errors: as
+ * steps, *nlog the number of rows; each row synchronises.  Synchronises at
+ * its end and returns ENONFINITE or EOVERFLOW when any build or walk of the
+ * run met that condition (a walk after such a build leaves acc/pot unwritten,
+ * so the state is then void); the next build does not hide it.  Errors: as
  * mibh_forces and mibh_energy, EINVAL for a short log. */
 mibh_status mibh_kick_drift(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_acc, int64_t n,
                             float dt_kick, float dt_drift);
@@ -234,7 +237,9 @@ mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float
  * dt_max and returns synchronised velocities, d_acc/d_pot at the final
  * positions and, when d_level is not NULL, the levels of the last step (uint8
  * [n]).  h_log (host, >= nbig + 1 rows, NULL: none) gets (t, T, W) in float64
- * at every multiple of dt_max.  Synchronises once per tick.  Errors: EINVAL
+ * at every multiple of dt_max.  Synchronises once per tick, and stops with
+ * ENONFINITE or EOVERFLOW at the first tick whose build, refit or walk met
+ * that condition (stats then hold the ticks run so far).  Errors: EINVAL
  * (parameters, pointers, n), as mibh_forces. */
 typedef struct {
     float dt_max;       /* largest step */

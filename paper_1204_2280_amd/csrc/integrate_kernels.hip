@@ -135,14 +135,18 @@ __global__ __launch_bounds__(256) void k_block_kick(float *__restrict__ vel, con
 
 // Work of the groups just walked (queue entries [0, *qlen)), work =
 // count * (1 + n_pc + n_pp): a group's first walk after a build stores its
-// reference; later walks add (now, reference) to the sums.
-__global__ __launch_bounds__(256) void k_rebuild_check(const uint32_t *__restrict__ order,
+// reference; later walks add (now, reference) to the sums.  After a build or
+// refit with a flagged condition the walk and its queue were skipped (the
+// queue and its length are stale), so this kernel skips too.
+__global__ __launch_bounds__(256) void k_rebuild_check(const Header *__restrict__ hdr,
+                                                       const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ qlen,
                                                        const uint2 *__restrict__ groups,
                                                        const uint2 *__restrict__ counts,
                                                        uint32_t *__restrict__ gref,
                                                        unsigned long long *__restrict__ sums) {
-    const unsigned nq = *qlen;
+    if (hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
+    const unsigned nq = min(*qlen, hdr->ngroups);
     unsigned long long now_sum = 0, ref_sum = 0;
     for (unsigned j = blockIdx.x * 256u + threadIdx.x; j < nq; j += gridDim.x * 256u) {
         const unsigned g = order[j];
@@ -193,8 +197,8 @@ hipError_t launch_block_kick(float *vel, const float *acc, uint8_t *level, unsig
 }
 
 hipError_t launch_rebuild_check(const Buffers &b, const uint32_t *qlen, unsigned long long *sums, hipStream_t s) {
-    hipLaunchKernelGGL(k_rebuild_check, dim3(256), dim3(256), 0, s, b.qorder, qlen, b.groups, b.gcounts, b.gref,
-                       sums);
+    hipLaunchKernelGGL(k_rebuild_check, dim3(256), dim3(256), 0, s, b.hdr, b.qorder, qlen, b.groups, b.gcounts,
+                       b.gref, sums);
     return hipGetLastError();
 }
 

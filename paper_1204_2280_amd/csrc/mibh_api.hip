@@ -39,7 +39,7 @@ struct mibh_ctx {
     int64_t n;
     const float *pos, *mass;
     float *acc, *pot;
-    double *h_energy;  // pinned 4 words: mibh_energy's two sums, or the block driver's counters
+    double *h_energy;  // pinned 8 words: mibh_energy's two sums, or the block driver's counters
     double *d_energy;  // 2 doubles in the workspace
     // stage events: MIBH_NSTAGES + 1 per profiled step
     hipEvent_t *events;
@@ -181,6 +181,20 @@ mibh_status flags_status(unsigned flags) {
     return MIBH_OK;
 }
 
+// Drivers running many builds: clears the sticky flags once the driver's first
+// build has moved the flags of earlier calls into them (stream order).
+hipError_t clear_sticky(mibh_ctx *ctx) {
+    return launch_fill_u32(&ctx->b.hdr->sticky, 1u, 0u, ctx->stream);
+}
+
+// Every condition met by any build since clear_sticky (syncs).
+mibh_status driver_flags(mibh_ctx *ctx) {
+    Header h;
+    mibh_status st = read_header(ctx, &h);
+    if (st) return st;
+    return flags_status(h.flags | h.sticky);
+}
+
 }  // namespace
 
 extern "C" {
@@ -243,10 +257,17 @@ mibh_status mibh_create(const mibh_params *pp, int64_t n_max, void *d_workspace,
     }
     layout(n_max, p, (char *)d_workspace, &c->b);
     c->d_energy = c->b.epart + 2 * ENERGY_BLOCKS;
-    e = hipHostMalloc((void **)&c->h_energy, 4 * sizeof(double), hipHostMallocDefault);
+    e = hipHostMalloc((void **)&c->h_energy, 8 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "hipHostMalloc");
+    }
+    // flags and sticky flags start clear (the workspace arrives uninitialised)
+    e = launch_fill_u32(reinterpret_cast<uint32_t *>(c->b.hdr), (unsigned)(sizeof(Header) / 4), 0u, c->stream);
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->h_energy);
+        delete c;
+        return hip_fail(e, "header fill");
     }
     *out = c;
     return MIBH_OK;
@@ -449,6 +470,7 @@ mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float
     };
     const float half = 0.5f * dt;
     if ((st = mibh_forces(ctx, d_pos, d_mass, n, theta, d_acc, d_pot))) return st;
+    HIP_TRY(clear_sticky(ctx), "sticky flags");
     if (log_every > 0 && (st = record(0))) return st;
     for (int s = 1; s <= nsteps; s++) {
         HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, (unsigned)n, half, dt, ctx->stream), "kick_drift");
@@ -456,7 +478,8 @@ mibh_status mibh_leapfrog(mibh_ctx *ctx, float *d_pos, float *d_vel, const float
         HIP_TRY(launch_kick_drift(d_pos, d_vel, d_acc, (unsigned)n, half, 0.0f, ctx->stream), "kick");
         if (log_every > 0 && s % log_every == 0 && (st = record(s))) return st;
     }
-    return MIBH_OK;
+    // a walk skips its work after a flagged build, so a flag of any step voids the run
+    return driver_flags(ctx);
 }
 
 mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const float *d_mass, int64_t n,
@@ -504,6 +527,7 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
         return MIBH_OK;
     };
     if ((st = mibh_build_tree(ctx, d_pos, d_mass, n))) return st;
+    HIP_TRY(clear_sticky(ctx), "sticky flags");
     if ((st = mibh_compute_multipoles(ctx))) return st;
     HIP_TRY(reset_refs(), "gref");
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->b.active), (un + 3u) / 4u, 0x01010101u, s), "due");
@@ -541,7 +565,16 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
             HIP_TRY(hipMemcpyAsync(&h_cnt[3], ctx->b.ohist + ORDER_BLOCKS, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                    s),
                     "hipMemcpyAsync(groups)");
+            HIP_TRY(hipMemcpyAsync(&h_cnt[4], &ctx->b.hdr->flags, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s),
+                    "hipMemcpyAsync(flags)");
             HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+            {  // the walk skipped its work after a flagged build or refit: stop here
+                const unsigned *fl = reinterpret_cast<const unsigned *>(&h_cnt[4]);
+                if ((st = flags_status(fl[0] | fl[1]))) {
+                    if (stats) *stats = stt;
+                    return st;
+                }
+            }
             const unsigned long long work_now = h_cnt[0], work_ref = h_cnt[1];
             stt.groups_walked += (int64_t)(uint32_t)h_cnt[3];
             rebuild = bp->rebuild_tol < 0.0f ||
@@ -563,9 +596,8 @@ mibh_status mibh_block_run(mibh_ctx *ctx, float *d_pos, float *d_vel, const floa
         }
     }
     if (d_level) HIP_TRY(hipMemcpyAsync(d_level, ctx->b.level, un, hipMemcpyDeviceToDevice, s), "levels out");
-    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (stats) *stats = stt;
-    return MIBH_OK;
+    return driver_flags(ctx);  // syncs
 }
 
 static mibh_status neighbors_check(mibh_ctx *ctx, const void *radius, const void *out) {

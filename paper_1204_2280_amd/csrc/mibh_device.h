@@ -45,10 +45,12 @@ constexpr int MLP_IN = 8, MLP_H = 64;   // work estimator 8 -> 64 -> 64 -> 1
 constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 4801
 constexpr int BBOX_MIN_BLOCKS = 16;     // bounding-box blocks per system at least
 
-// Device-resident per-context state, rewritten by every build.
+// Device-resident per-context state, rewritten by every build (zeroed once
+// when the context is created).
 struct Header {
     unsigned nsys;          // systems in the current batch (1 for a single system)
-    unsigned flags;
+    unsigned flags;         // conditions met since the current build started
+    unsigned sticky;        // flags of the earlier builds since the drivers last cleared it
     unsigned n;
     unsigned ncells;
     unsigned ngroups;

@@ -229,10 +229,13 @@ __global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ pa
     }
 }
 
-// Header reset, before the per-system reductions of one build.
+// Header reset, before the per-system reductions of one build.  The flags of
+// the previous build move into the sticky word, so that a driver running many
+// steps still sees a condition that one of its earlier builds met.
 __global__ void k_header_reset(unsigned n, unsigned nsys, Header *__restrict__ hdr) {
     if (threadIdx.x == 0) {
         hdr->nsys = nsys;
+        hdr->sticky |= hdr->flags;
         hdr->flags = 0;
         hdr->n = n;
         hdr->ncells = 0;

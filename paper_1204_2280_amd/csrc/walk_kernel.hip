@@ -593,11 +593,16 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_order_hist(OrderArgs o, uint3
 }
 
 // Exclusive prefix sum, in place, of ohist[ORDER_BUCKETS][ORDER_BLOCKS] read
-// as one row-major sequence.
-__global__ __launch_bounds__(ORDER_SCAN_THREADS) void k_order_scan(uint32_t *__restrict__ ohist) {
+// as one row-major sequence.  It skips with the histogram and scatter kernels:
+// run on a table the histogram did not refill, it would scan the previous
+// prefix sums again, and the queue length it leaves (ohist[ORDER_BLOCKS] in the
+// active mode) would exceed the number of groups.
+__global__ __launch_bounds__(ORDER_SCAN_THREADS) void k_order_scan(const Header *__restrict__ hdr,
+                                                                   uint32_t *__restrict__ ohist) {
     constexpr int PER = ORDER_BUCKETS * ORDER_BLOCKS / ORDER_SCAN_THREADS;
     static_assert(PER * ORDER_SCAN_THREADS == ORDER_BUCKETS * ORDER_BLOCKS, "scan covers the table");
     __shared__ unsigned s_w[ORDER_SCAN_THREADS / 64];
+    if (hdr->flags & ORDER_SKIP) return;
     const unsigned t = threadIdx.x, ln = lane64(), w = t >> 6;
     unsigned v[PER], sum = 0;
 #pragma unroll
@@ -677,7 +682,7 @@ hipError_t launch_queue_order(const Buffers &b, int mode, const uint8_t *active,
     o.active = active;
     o.mode = mode;
     hipLaunchKernelGGL(k_order_hist, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, o, b.ohist);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(ORDER_SCAN_THREADS), 0, s, b.ohist);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(ORDER_SCAN_THREADS), 0, s, b.hdr, b.ohist);
     hipLaunchKernelGGL(k_order_scatter, dim3(ORDER_BLOCKS), dim3(ORDER_THREADS), 0, s, o, b.ohist, b.qorder);
     return hipGetLastError();
 }

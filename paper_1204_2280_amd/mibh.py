@@ -67,6 +67,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1204_2280_amd.build.build()")
+        # torch carries a HIP runtime of its own (soname libamdhip64.so) beside the
+        # system one this library links (libamdhip64.so.7).  Loaded before torch's
+        # runtime had started, the library's runtime found no device; so torch's
+        # starts first (on a machine without a GPU this only returns False).
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, i64, st = C.c_void_p, C.c_int64, C.c_int
         L.mibh_default_params.argtypes = [C.POINTER(Params)]

@@ -77,3 +77,24 @@ def test_block_run_argument_errors():
         args.update(kw)
         with pytest.raises(mibh.MibhError):
             ctx.block_run(P, V, M, 0.75, args["dt_max"], args["max_level"], args["eta"], args["eps"], 1)
+
+
+def test_block_run_stops_when_the_state_turns_nonfinite():
+    """A NaN velocity makes one position NaN at the first drift; the first
+    tick with a due particle refits a tree with it, its walk does nothing, and
+    the driver stops there with ENONFINITE.  A clean run on the same context
+    afterwards returns normally."""
+    import torch
+    from paper_1204_2280_amd import mibh
+    pos, vel, mass = W.plummer(2000, 6)
+    bad = vel.copy()
+    bad[5, 2] = np.nan
+    ctx = gpu_context(len(mass), eps2=1e-4)
+    M = _t(mass)
+    print("[gpu] block run with a NaN velocity, R=2, 1 step", flush=True)
+    with pytest.raises(mibh.MibhError) as ei:
+        ctx.block_run(_t(pos), _t(bad), M, 0.75, 1 / 16, 2, 0.1, 0.1, 1)
+    assert ei.value.status == -6
+    P = _t(pos)
+    ctx.block_run(P, _t(vel), M, 0.75, 1 / 16, 2, 0.1, 0.1, 1)
+    assert bool(torch.isfinite(P).all())

@@ -84,3 +84,26 @@ def test_leapfrog_argument_errors():
         ctx.leapfrog(P, V, M, 0.75, 0.01, -1)
     with pytest.raises(ValueError):
         ctx.kick_drift(P, V[:5], P, 0.1, 0.1)
+
+
+def test_leapfrog_reports_a_state_that_turns_nonfinite_mid_run():
+    """A NaN velocity makes one position NaN at the first drift; the walks
+    after that build do nothing, and the driver must say so (ENONFINITE) even
+    though later builds reset the per-build flags.  The context stays usable:
+    a clean run on it afterwards returns normally."""
+    import torch
+    from paper_1204_2280_amd import mibh
+    pos, vel, mass = W.plummer(2000, 5)
+    bad = vel.copy()
+    bad[17, 0] = np.nan
+    ctx = gpu_context(len(mass))
+    M = torch.from_numpy(mass).cuda()
+    P, V = torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(bad).cuda()
+    print("[gpu] leapfrog with a NaN velocity, 3 steps, no energy log", flush=True)
+    with pytest.raises(mibh.MibhError) as ei:
+        ctx.leapfrog(P, V, M, 0.75, 1 / 64, 3)
+    assert ei.value.status == -6
+    P, V = torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda()
+    ctx.leapfrog(P, V, M, 0.75, 1 / 64, 3)
+    ctx.sync()
+    assert bool(torch.isfinite(P).all())

@@ -149,6 +149,29 @@ mibh_status mibh_compute_forces_active(mibh_ctx *ctx, float theta, const uint8_t
 mibh_status mibh_forces(mibh_ctx *ctx, const float *d_pos, const float *d_mass, int64_t n,
                         float theta, float *d_acc, float *d_pot);
 
+/* The force step for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same result as mibh_forces with default parameters (ncrit 16, groups of
+ * <= 64, eps2 0, G 1, plain float32 accumulation), bit for bit, for
+ * 1 <= n <= mibh_static_n_max() (32768) particles; larger n gives EINVAL.
+ * Inputs and outputs are the caller's device arrays, laid out as for
+ * mibh_forces; work is enqueued on `stream` (a hipStream_t, NULL: the null
+ * stream) and the call does not synchronise.  The workspace is a file-scope
+ * device array of mibh_static_bytes() (40 MiB) that every GPU the library
+ * runs on holds from module load until the process ends; the call allocates
+ * nothing (no hipMalloc, no host allocation).  All calls on one GPU share that
+ * array and the host state that describes it: calls that overlap on one GPU
+ * (two streams, or a second call before the first has finished on its
+ * stream) race and give undefined results; calls from several host threads
+ * are serialised while they enqueue, not while they run.  Device-side
+ * conditions (non-finite input, negative mass) leave acc/pot unwritten and are
+ * not reported by this call.  Errors: EINVAL (null pointer, n out of range,
+ * theta <= 0 or non-finite), EHIP. */
+mibh_status mibh_forces_static(const float *d_pos, const float *d_mass, int64_t n, float theta, float *d_acc,
+                               float *d_pot, void *stream);
+size_t mibh_static_bytes(void);
+int64_t mibh_static_n_max(void);
+
 /* Graph capture of one whole step: build (batched, as mibh_build_tree_batch),
  * multipoles and forces are captured from the context's stream into a HIP graph
  * and instantiated; nothing runs during the capture.  mibh_graph_launch replays

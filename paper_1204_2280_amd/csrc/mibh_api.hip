@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 using namespace mibh;
@@ -957,6 +958,87 @@ mibh_status mibh_fma_probe(float *d_out, int32_t blocks, int32_t iters, float a,
     if (blocks < 1 || blocks > (1 << 20) || iters < 0) return fail(MIBH_EINVAL, "blocks or iters out of range");
     HIP_TRY(launch_fma_probe(d_out, (unsigned)blocks, (unsigned)iters, a, b, (hipStream_t)stream), "fma_probe");
     return MIBH_OK;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// The force step without allocation (mibh_forces_static).  Its workspace is
+// the file-scope device array `scratch`; every GPU the library runs on holds
+// its own copy from module load until the process ends.  Host code never
+// passes the array's name to a kernel or copy: at the first call on a device
+// (that device current) hipGetSymbolAddress gives that device's address,
+// which is kept per device and carved like a caller's workspace.
+// --------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t STATIC_N_MAX = 32768;       // particles per call at most
+constexpr int STATIC_WALK_WAVES = 512;        // persistent walk waves (spill stacks are per wave)
+constexpr size_t STATIC_BYTES = 40ull << 20;  // >= the layout of (STATIC_N_MAX, STATIC_WALK_WAVES)
+constexpr int STATIC_DEVICES = 64;
+
+struct StaticSlot {
+    std::mutex mu;
+    bool ready;
+    mibh_ctx ctx;
+};
+StaticSlot g_static[STATIC_DEVICES];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+
+extern "C" {
+
+size_t mibh_static_bytes(void) { return STATIC_BYTES; }
+
+int64_t mibh_static_n_max(void) { return STATIC_N_MAX; }
+
+mibh_status mibh_forces_static(const float *d_pos, const float *d_mass, int64_t n, float theta, float *d_acc,
+                               float *d_pot, void *stream) {
+    if (!d_pos || !d_mass || !d_acc || !d_pot) return fail(MIBH_EINVAL, "null pointer");
+    if (n < 1 || n > STATIC_N_MAX)
+        return fail(MIBH_EINVAL, "n = %lld outside [1, %lld], the limit of the static workspace", (long long)n,
+                    (long long)STATIC_N_MAX);
+    if (!(theta > 0.0f) || !isfinite(theta)) return fail(MIBH_EINVAL, "theta must be finite and > 0");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= STATIC_DEVICES) return fail(MIBH_EINVAL, "device %d beyond the static slots", dev);
+    StaticSlot &slot = g_static[dev];
+    std::lock_guard<std::mutex> lock(slot.mu);
+    mibh_ctx *c = &slot.ctx;
+    if (!slot.ready) {
+        mibh_default_params(&c->p);
+        c->p.walk_waves = STATIC_WALK_WAVES;
+        const size_t need = layout(STATIC_N_MAX, c->p, nullptr, nullptr);
+        if (need > STATIC_BYTES)
+            return fail(MIBH_ENOMEM, "static workspace too small: %zu < %zu bytes", STATIC_BYTES, need);
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr || ((uintptr_t)ptr % ALIGN) != 0) return fail(MIBH_EHIP, "static workspace address not aligned");
+        c->n_max = STATIC_N_MAX;
+        c->device = dev;
+        c->nsys = 1;
+        c->order = c->last_order = MIBH_ORDER_MORTON;
+        c->est_w16 = nullptr;
+        c->counts_valid = 0;
+        c->graph = nullptr;
+        c->graph_exec = nullptr;
+        c->h_energy = nullptr;  // this entry point never synchronises
+        c->events = nullptr;
+        c->prof_max = c->prof_step = 0;
+        c->prof_last = -2;
+        layout(STATIC_N_MAX, c->p, (char *)ptr, &c->b);
+        c->d_energy = c->b.epart + 2 * ENERGY_BLOCKS;
+        // flags start clear: a kernel fill, also on a stream being captured
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->b.hdr), (unsigned)(sizeof(Header) / 4), 0u,
+                                (hipStream_t)stream),
+                "header fill");
+        slot.ready = true;
+    }
+    c->stream = (hipStream_t)stream;
+    c->state = 0;
+    return mibh_forces(c, d_pos, d_mass, n, theta, d_acc, d_pot);
 }
 
 const char *mibh_status_string(mibh_status s) {

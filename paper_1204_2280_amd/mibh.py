@@ -129,6 +129,12 @@ def lib():
         for f in ("mibh_group_features", "mibh_set_queue_order", "mibh_mlp_forward", "mibh_mlp_gradient",
                   "mibh_mlp_adam"):
             getattr(L, f).restype = st
+        L.mibh_forces_static.argtypes = [P, P, i64, C.c_float, P, P, P]
+        L.mibh_forces_static.restype = st
+        L.mibh_static_bytes.argtypes = []
+        L.mibh_static_bytes.restype = C.c_size_t
+        L.mibh_static_n_max.argtypes = []
+        L.mibh_static_n_max.restype = i64
         L.mibh_fma_probe.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
         L.mibh_fma_probe.restype = st
         L.mibh_profile_begin.argtypes = [P, C.c_int]
@@ -173,6 +179,32 @@ def _require(t, dtype, shape_tail, device, name):
         raise ValueError(f"{name} must be a contiguous {dtype} tensor on {device}")
     if tuple(t.shape[1:]) != shape_tail:
         raise ValueError(f"{name} has shape {tuple(t.shape)}")
+
+
+def forces_static(pos, mass, theta: float, acc, pot, stream=None):
+    """mibh_forces_static: the force step on the library's static workspace
+    (n <= static_n_max(), default parameters).  pos [n,3], mass [n], acc [n,3]
+    and pot [n] are caller-allocated float32 tensors on the current device;
+    the call enqueues on `stream` (default: the current stream) and allocates
+    nothing."""
+    import torch
+    dev = pos.device
+    n = int(mass.shape[0])
+    for t, name, tail in ((pos, "pos", (3,)), (acc, "acc", (3,))):
+        _require(t, torch.float32, tail, dev, name)
+    for t, name in ((mass, "mass"), (pot, "pot")):
+        _require(t, torch.float32, (), dev, name)
+    if pos.shape[0] != n or acc.shape[0] != n or pot.shape[0] != n:
+        raise ValueError("pos, mass, acc and pot sizes differ")
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(lib().mibh_forces_static(pos.data_ptr(), mass.data_ptr(), n, float(theta), acc.data_ptr(),
+                                        pot.data_ptr(), s.cuda_stream))
+    return acc, pot
+
+
+def static_n_max() -> int:
+    return int(lib().mibh_static_n_max())
 
 
 class Context:

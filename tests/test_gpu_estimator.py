@@ -156,8 +156,8 @@ def test_queue_orders_change_nothing_but_the_order():
 def test_two_spheres_full_size():
     """The queue-order benchmark's workload (two Plummer spheres of 2^21, the
     benchmark's configuration): Morton and exact-count (heaviest first) orders
-    give bit-identical forces and counts, and sampled group ranges match the
-    oracle (counts bit for bit, forces within 1e-5 at p99)."""
+    give bit-identical forces and counts, and every group matches the oracle
+    (counts bit for bit, forces of all particles within 1e-5 at p99)."""
     torch = _torch()
     import oracle
     from gpu_helpers import TOL_P99, p99, rel_err
@@ -177,26 +177,15 @@ def test_two_spheres_full_size():
     ctx.sync()
     assert torch.equal(acc0, acc1) and torch.equal(pot0, pot1)
     np.testing.assert_array_equal(ctx.export("counts").view(torch.int32).cpu().numpy(), c0)
+    print(f"[gpu] two spheres: oracle walk of every group", flush=True)
     T = oracle.Tree(pos, mass)
-    grp = T.groups()
-    ga, gp = acc0.cpu().numpy().astype(np.float64), pot0.cpu().numpy().astype(np.float64)
-    acc_g, pot_g, acc_o, pot_o = [], [], [], []
-    width = 160
-    for s0 in np.linspace(0, T.ngroups - width, 8).astype(np.int64):
-        gb, ge = int(s0), int(s0) + width
-        T.walk(0.75, groups=(gb, ge))
-        npc, npp = T.counts()
-        np.testing.assert_array_equal(c0[gb:ge, 0], npc[gb:ge])
-        np.testing.assert_array_equal(c0[gb:ge, 1], npp[gb:ge])
-        sacc, spot = T.sorted_forces()
-        f0, f1 = grp["first"][gb], grp["first"][ge - 1] + grp["count"][ge - 1]
-        idx = T.perm[f0:f1]
-        acc_o.append(sacc[f0:f1])
-        pot_o.append(spot[f0:f1])
-        acc_g.append(ga[idx])
-        pot_g.append(gp[idx])
-    ea = rel_err(np.concatenate(acc_g), np.concatenate(acc_o))
-    ep = rel_err(np.concatenate(pot_g), np.concatenate(pot_o))
-    print(f"[gpu] two spheres: {ea.size} sampled particles, acc p99 {p99(ea):.2e}, pot p99 {p99(ep):.2e}",
-          flush=True)
+    T.walk(0.75)
+    npc, npp = T.counts()
+    np.testing.assert_array_equal(c0[:, 0], npc)
+    np.testing.assert_array_equal(c0[:, 1], npp)
+    acc_o, pot_o = T.forces()
+    ea = rel_err(acc0.cpu().numpy().astype(np.float64), acc_o)
+    ep = rel_err(pot0.cpu().numpy().astype(np.float64), pot_o)
+    print(f"[gpu] two spheres: all {ea.size} particles, acc p99 {p99(ea):.2e}, pot p99 {p99(ep):.2e}", flush=True)
+    assert ea.size == n
     assert p99(ea) <= TOL_P99 and p99(ep) <= TOL_P99

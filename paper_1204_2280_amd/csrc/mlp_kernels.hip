@@ -22,8 +22,13 @@ static_assert(OFF_B3 + 1 == MLP_NPARAM, "parameter layout");
 // extent and distance to the system's centre of mass (in root-cube units),
 // local density relative to the system's mean, theta, group level, system
 // size.  All are O(1) by construction so that no data-dependent
-// normalisation is needed.
+// normalisation is needed.  The group's box is gathered 8 particles per round
+// with the indices clamped to the group's last particle (a repeated particle
+// leaves a minimum or maximum unchanged), so each round issues its 8 loads at
+// once and a group of n particles takes ceil(n / 8) round trips.
 // --------------------------------------------------------------------------
+
+constexpr unsigned FEAT_BATCH = 8;
 
 __global__ __launch_bounds__(256) void k_features(const Header *__restrict__ hdr, const SysCube *__restrict__ cube,
                                                   const uint2 *__restrict__ groups, const uint4 *__restrict__ topo,
@@ -34,10 +39,15 @@ __global__ __launch_bounds__(256) void k_features(const Header *__restrict__ hdr
         const uint2 gr = groups[g];
         const unsigned gf = gr.x, gn = gr.y & 255u, glev = (gr.y >> 8) & 255u, sys = gr.y >> 16;
         float3 bmin = make_float3(INFINITY, INFINITY, INFINITY), bmax = make_float3(-INFINITY, -INFINITY, -INFINITY);
-        for (unsigned j = gf; j < gf + gn; j++) {
-            const float4 p = spos[j];
-            bmin.x = fminf(bmin.x, p.x); bmin.y = fminf(bmin.y, p.y); bmin.z = fminf(bmin.z, p.z);
-            bmax.x = fmaxf(bmax.x, p.x); bmax.y = fmaxf(bmax.y, p.y); bmax.z = fmaxf(bmax.z, p.z);
+        for (unsigned j0 = 0; j0 < gn; j0 += FEAT_BATCH) {
+            float4 p[FEAT_BATCH];
+#pragma unroll
+            for (unsigned u = 0; u < FEAT_BATCH; u++) p[u] = spos[gf + min(j0 + u, gn - 1u)];
+#pragma unroll
+            for (unsigned u = 0; u < FEAT_BATCH; u++) {
+                bmin.x = fminf(bmin.x, p[u].x); bmin.y = fminf(bmin.y, p[u].y); bmin.z = fminf(bmin.z, p[u].z);
+                bmax.x = fmaxf(bmax.x, p[u].x); bmax.y = fmaxf(bmax.y, p[u].y); bmax.z = fmaxf(bmax.z, p[u].z);
+            }
         }
         const float L = ldexpf(1.0f, cube[sys].k);
         const float ext = fmaxf(fmaxf(bmax.x - bmin.x, bmax.y - bmin.y), bmax.z - bmin.z);
@@ -61,7 +71,15 @@ __global__ __launch_bounds__(256) void k_features(const Header *__restrict__ hdr
 }
 
 // --------------------------------------------------------------------------
-// Forward pass, one row per thread; weights converted once into LDS.
+// Forward pass, one row per thread; weights converted once into LDS and read
+// back as wave-uniform (broadcast) loads.  The hidden layers run as outer
+// products: hidden unit j of the first layer is computed on its own, then
+// added into the 64 second-layer sums, whose weights W2[.][j] sit transposed
+// in LDS (16 broadcast loads of 4).  Each sum keeps the order of its dot
+// product (bias first, then j = 0..63), so the predictions equal those of
+// plain dot products bit for bit.  A fully unrolled first layer made the
+// compiler keep 488 registers (one wave per SIMD); this form takes 221 (two
+// waves per SIMD; bounds asking for three or four waves make it spill).
 // --------------------------------------------------------------------------
 
 __device__ __forceinline__ void load_weights(const __half *__restrict__ w16, float *s_w) {
@@ -69,35 +87,54 @@ __device__ __forceinline__ void load_weights(const __half *__restrict__ w16, flo
     __syncthreads();
 }
 
-__device__ __forceinline__ float mlp_row(const float *s_w, const float *x, float *h1) {
-#pragma unroll
-    for (int i = 0; i < MLP_H; i++) {
-        float s = s_w[OFF_B1 + i];
-#pragma unroll
-        for (int k = 0; k < MLP_IN; k++) s = fmaf(s_w[OFF_W1 + i * MLP_IN + k], x[k], s);
-        h1[i] = fmaxf(s, 0.0f);
+// LDS image for the forward pass: W1, b1 as stored, W2 transposed, b2, w3, b3.
+static_assert(OFF_W2 % 4 == 0, "float4 reads of the transposed second layer");
+constexpr int FWD_W2T = OFF_W2;
+
+__device__ __forceinline__ void load_weights_fwd(const __half *__restrict__ w16, float *s_w) {
+    for (int i = threadIdx.x; i < MLP_NPARAM; i += blockDim.x) {
+        int d = i;
+        if (i >= OFF_W2 && i < OFF_B2) {  // W2[r][c] -> W2T[c][r]
+            const int r = (i - OFF_W2) / MLP_H, c = (i - OFF_W2) % MLP_H;
+            d = FWD_W2T + c * MLP_H + r;
+        }
+        s_w[d] = __half2float(w16[i]);
     }
-    float y = s_w[OFF_B3];
-    for (int i = 0; i < MLP_H; i++) {
-        float s = s_w[OFF_B2 + i];
-#pragma unroll
-        for (int j = 0; j < MLP_H; j++) s = fmaf(s_w[OFF_W2 + i * MLP_H + j], h1[j], s);
-        y = fmaf(s_w[OFF_W3 + i], fmaxf(s, 0.0f), y);
-    }
-    return y;
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void k_mlp_fwd(const __half *__restrict__ w16, const float *__restrict__ x,
                                                  unsigned rows, const Header *__restrict__ hdr,
                                                  float *__restrict__ y) {
-    __shared__ float s_w[MLP_NPARAM];
-    load_weights(w16, s_w);
+    __shared__ __align__(16) float s_w[MLP_NPARAM];
+    load_weights_fwd(w16, s_w);
     const unsigned nrows = hdr ? hdr->ngroups : rows;
     for (unsigned r = blockIdx.x * 256u + threadIdx.x; r < nrows; r += gridDim.x * 256u) {
-        float xi[MLP_IN], h1[MLP_H];
+        float xi[MLP_IN], h2[MLP_H];
 #pragma unroll
         for (int k = 0; k < MLP_IN; k++) xi[k] = x[(size_t)r * MLP_IN + k];
-        y[r] = mlp_row(s_w, xi, h1);
+#pragma unroll
+        for (int i = 0; i < MLP_H; i++) h2[i] = s_w[OFF_B2 + i];
+#pragma nounroll
+        for (int j = 0; j < MLP_H; j++) {
+            float a = s_w[OFF_B1 + j];
+#pragma unroll
+            for (int k = 0; k < MLP_IN; k++) a = fmaf(s_w[OFF_W1 + j * MLP_IN + k], xi[k], a);
+            const float h1j = fmaxf(a, 0.0f);
+            const float4 *col = reinterpret_cast<const float4 *>(s_w + FWD_W2T + j * MLP_H);
+#pragma unroll
+            for (int q = 0; q < MLP_H / 4; q++) {
+                const float4 w = col[q];
+                h2[4 * q] = fmaf(w.x, h1j, h2[4 * q]);
+                h2[4 * q + 1] = fmaf(w.y, h1j, h2[4 * q + 1]);
+                h2[4 * q + 2] = fmaf(w.z, h1j, h2[4 * q + 2]);
+                h2[4 * q + 3] = fmaf(w.w, h1j, h2[4 * q + 3]);
+            }
+        }
+        float out = s_w[OFF_B3];
+#pragma unroll
+        for (int i = 0; i < MLP_H; i++) out = fmaf(s_w[OFF_W3 + i], fmaxf(h2[i], 0.0f), out);
+        y[r] = out;
     }
 }
 

@@ -31,6 +31,34 @@ WALK_SOURCES = ("paper_1204_2280_amd/csrc/walk_kernel.hip", "paper_1204_2280_amd
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_hbm_traffic.json")
 
 
+PEAK_HBM_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+# Algorithmic HBM bytes of the tree stages: per particle, per radix pass and per cell.
+#   sorting: bounding box reads x, y, z, m (16); keys read them again and write the
+#     key (8) and the packed record (16); each of the 8 radix passes (60-bit keys in
+#     8-bit digits) reads the key for the histogram (8), reads key + index (12) and
+#     writes them (12);
+#   moving: index (4), gathered record (16), written record (16);
+#   tree construction: keys and the common-prefix byte read (9), level record
+#     written and read (8), groups written (8), plus one 16-byte topology record per cell;
+#   multipoles: sorted records read (16) plus per cell the topology (16), float64
+#     moments, delta and l' written (96) and read back by the parent (96), the
+#     particle box (24) and the walk data (48) written.
+HBM_B_PER_PARTICLE = {"sorting": 16 + 40 + 8 * 32, "moving": 36, "tree_construction": 25, "multipoles": 16}
+HBM_B_PER_CELL = {"tree_construction": 16, "multipoles": 16 + 96 + 96 + 24 + 48}
+
+
+def hbm_stages(stage_ms, n, ncells):
+    """Achieved algorithmic bandwidth of each tree stage against 8 TB/s."""
+    out = {}
+    for k, bp in HBM_B_PER_PARTICLE.items():
+        ms = stage_ms[k] + (stage_ms["mac_prep"] if k == "multipoles" else 0.0)
+        b = bp * n + HBM_B_PER_CELL.get(k, 0) * ncells
+        gbs = b / (ms * 1e-3) / 1e9
+        out[k] = {"bytes": b, "ms": ms, "GB/s": gbs, "frac": gbs / PEAK_HBM_GBS}
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -166,9 +194,13 @@ def bench_variant_kahan(pos, mass, theta, steps, warmup):
     return {"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3)}
 
 
-def bench_variant_ensemble(theta, steps, warmup, nsys=64, seed=4):
+def bench_variant_ensemble(theta, steps, warmup, w16, nsys=64, seed=4, rounds=3):
     """Batched ensemble (uneven N, half Plummer, half Hernquist truncated at 50):
-    one graph-replayed batched step vs one single-system step per system."""
+    one graph-replayed batched step vs one single-system step per system; the
+    graph-replayed step in four configurations (plain or Kahan accumulation,
+    Morton or learned-estimator queue order) timed in alternation, medians of
+    `rounds` rounds.  Returns (record, outputs): outputs holds the plain and
+    the Kahan + estimator forces for the oracle comparison of the CPU leg."""
     import numpy as np
     import torch
     from paper_1204_2280_amd import mibh, workloads
@@ -224,23 +256,86 @@ def bench_variant_ensemble(theta, steps, warmup, nsys=64, seed=4):
         b.record(stream)
         torch.cuda.synchronize()
         ms_tuned = a.elapsed_time(b) / steps
-    return {"workload": f"ensemble_{nsys}sys_seed{seed}_n{n}_theta{theta:g}", "n": n, "nsys": nsys,
+        del tuned, single
+        # the four configurations, one context each, timed in alternation
+        cfgs = {}
+        for name, prec, w in (("plain_morton", mibh.PLAIN, None), ("kahan_morton", mibh.KAHAN, None),
+                              ("plain_estimator", mibh.PLAIN, w16), ("kahan_estimator", mibh.KAHAN, w16)):
+            c = mibh.Context(n, device=dev, stream=stream, max_systems=nsys, precision=prec)
+            if w is not None:
+                c.set_queue_order(mibh.ORDER_ESTIMATOR, w)
+            ca = torch.empty((n, 3), dtype=torch.float32, device=dev)
+            cq = torch.empty((n,), dtype=torch.float32, device=dev)
+            c.graph_capture(p, m, off, theta, ca, cq)
+            for _ in range(warmup):
+                c.graph_launch()
+            cfgs[name] = (c, ca, cq, [])
+        for _ in range(rounds):
+            for name, (c, ca, cq, times) in cfgs.items():
+                c.graph_launch()
+                a.record(stream)
+                for _ in range(steps):
+                    c.graph_launch()
+                b.record(stream)
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b) / steps)
+        configs = {name: {"ms_per_step": float(np.median(t)), "particles_per_s": n / (float(np.median(t)) * 1e-3)}
+                   for name, (_, _, _, t) in cfgs.items()}
+        outputs = {name: (cfgs[name][1].cpu().numpy(), cfgs[name][2].cpu().numpy())
+                   for name in ("plain_morton", "kahan_estimator")}
+        del cfgs
+    rec = {"workload": f"ensemble_{nsys}sys_seed{seed}_n{n}_theta{theta:g}", "n": n, "nsys": nsys,
             "autotuned": best, "ms_per_step_tuned_graph": ms_tuned,
             "particles_per_s_tuned_graph": n / (ms_tuned * 1e-3),
             "ms_per_step_batched_graph": ms_batch, "particles_per_s_batched_graph": n / (ms_batch * 1e-3),
             "ms_per_step_sequential": ms_seq, "particles_per_s_sequential": n / (ms_seq * 1e-3),
             "speedup": ms_seq / ms_batch, "interactions_per_s_batched":
-                (st["sum_pc"] + st["sum_pp"]) / (ms_batch * 1e-3)}
+                (st["sum_pc"] + st["sum_pp"]) / (ms_batch * 1e-3),
+            "graph_configs": configs,
+            "graph_configs_timing": f"{rounds} alternating rounds x {steps} replays per configuration, medians"}
+    return rec, outputs
 
 
-def bench_variant_queue_order(pos_train, mass_train, theta, steps, warmup):
-    """Walk time for the three queue orders on two Plummer spheres of 2^21
-    particles each (seeds 5 and 6, 10 apart): Morton; longest-processing-time
-    first by the exact counts of the previous walk of the same tree; and by the
-    learned estimator, trained on the per-group counts of Plummer spheres of
-    2^15 (seed 1), 2^20 (seed 2) and the headline 2^22 system (given).  The
-    step time with the estimator includes its feature and forward kernels (in
-    the mac_prep stage)."""
+def _p99_rel(a, ref):
+    """99th percentile (nearest rank) of |a_i - ref_i| / |ref_i| over rows."""
+    import numpy as np
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    num = np.linalg.norm(a - ref, axis=1) if a.ndim == 2 else np.abs(a - ref)
+    den = np.linalg.norm(ref, axis=1) if ref.ndim == 2 else np.abs(ref)
+    e = np.sort(num / np.where(den > 0, den, 1.0))
+    return float(e[int(np.ceil(0.99 * e.size)) - 1])
+
+
+def cpu_baseline_ensemble(theta, outputs, nsys=64, seed=4):
+    """The float64 oracle on the ensemble: every system's tree and walk, timed
+    on the host cores; the GPU's plain and Kahan + estimator forces are scored
+    against its results (relative error, 99th percentile over all particles)."""
+    import numpy as np
+    import oracle
+    from paper_1204_2280_amd import workloads
+    pos, mass, off = workloads.ensemble(nsys, seed)
+    n = int(off[-1])
+    acc = np.empty((n, 3))
+    pot = np.empty(n)
+    t0 = time.perf_counter()
+    for k in range(nsys):
+        a, b = int(off[k]), int(off[k + 1])
+        T = oracle.Tree(pos[a:b], mass[a:b])
+        T.walk(theta)
+        acc[a:b], pot[a:b] = T.forces()
+        del T
+    t = time.perf_counter() - t0
+    return {"value": n / t, "unit": "particles/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"the whole ensemble: {nsys} systems, {n} particles, tree and walk in {t:.2f} s",
+            "acc_p99_vs_oracle": {k: _p99_rel(v[0], acc) for k, v in outputs.items()},
+            "pot_p99_vs_oracle": {k: _p99_rel(v[1], pot) for k, v in outputs.items()}}
+
+
+def train_estimator(pos_train, mass_train, theta):
+    """The learned work estimator, trained on the GPU on the per-group counts of
+    Plummer spheres of 2^15 (seed 1), 2^20 (seed 2) and the headline 2^22 system
+    (given): returns its float16 weights."""
     import torch
     from paper_1204_2280_amd import estimator, mibh, workloads
     dev = torch.device("cuda", 0)
@@ -256,38 +351,69 @@ def bench_variant_queue_order(pos_train, mass_train, theta, steps, warmup):
         ts.append(t)
         del c
     _, w16, _ = estimator.train(torch.cat(xs), torch.cat(ts), steps=1000, batch=1024, lr=3e-3)
+    return w16
+
+
+def bench_variant_queue_order(w16, theta, steps, rounds=5):
+    """Queue orders on two Plummer spheres of 2^21 particles each (seeds 5 and 6,
+    10 apart): Morton; longest-processing-time first by the exact counts of the
+    previous walk of the same tree; and by the learned estimator.  The three are
+    timed in alternation (rounds x steps each) from the library's stage events;
+    "order_and_walk_ms" is the MAC-data stage (which holds the estimator's
+    feature and forward kernels and the ordering kernels) plus the walk, the
+    part of a step that the order changes; the estimator and Morton steps are
+    also timed whole.  Medians over all timed steps."""
+    import numpy as np
+    import torch
+    from paper_1204_2280_amd import estimator, mibh, workloads
+    dev = torch.device("cuda", 0)
     pos, mass = workloads.two_plummers(1 << 21)
     n = len(mass)
     p = torch.from_numpy(pos).to(dev)
     m = torch.from_numpy(mass).to(dev)
     ctx = mibh.Context(n, device=dev)
 
-    def stages(run):
-        for _ in range(warmup):
-            run()
-        ctx.sync()
-        ctx.profile_begin(steps)
-        for _ in range(steps):
-            run()
-        rec = ctx.profile_read()
-        return {k: sum(r[k] for r in rec) / len(rec) for k in rec[0]}
+    def run_mode(mode):
+        if mode == "morton":
+            ctx.set_queue_order(mibh.ORDER_MORTON)
+            return lambda: ctx.forces(p, m, theta)
+        if mode == "estimator":
+            ctx.set_queue_order(mibh.ORDER_ESTIMATOR, w16)
+            return lambda: ctx.forces(p, m, theta)
+        ctx.set_queue_order(mibh.ORDER_EXACT)
+        ctx.forces(p, m, theta)
+        ctx.compute_forces(theta)  # exact counts of this tree
+        return lambda: ctx.compute_forces(theta)
 
+    rec = {k: [] for k in ("morton", "estimator", "exact")}
+    for r in range(rounds + 1):
+        for mode in rec:
+            fn = run_mode(mode)
+            fn()
+            ctx.sync()
+            ctx.profile_begin(steps)
+            for _ in range(steps):
+                fn()
+            got = ctx.profile_read()
+            if r > 0:  # round 0 warms every mode up
+                rec[mode].extend(got)
     out = {}
-    ctx.set_queue_order(mibh.ORDER_MORTON)
-    st = stages(lambda: ctx.forces(p, m, theta))
-    out["morton"] = {"walk_ms": st["walk"], "step_ms": sum(st.values())}
-    ctx.set_queue_order(mibh.ORDER_ESTIMATOR, w16)
-    st = stages(lambda: ctx.forces(p, m, theta))
-    out["estimator"] = {"walk_ms": st["walk"], "mac_prep_ms": st["mac_prep"], "step_ms": sum(st.values())}
+    for mode, rows in rec.items():
+        med = {k: float(np.median([x[k] for x in rows])) for k in rows[0]}
+        d = {"walk_ms": med["walk"], "mac_prep_ms": med["mac_prep"],
+             "order_and_walk_ms": float(np.median([x["mac_prep"] + x["walk"] for x in rows]))}
+        if mode != "exact":
+            d["step_ms"] = float(np.median([sum(x.values()) for x in rows]))
+        out[mode] = d
+    out["exact"]["note"] = "repeated walks of one tree (the counts of a new tree are not known before its walk)"
     x, t = estimator.collect(ctx, theta)
     out["estimator"]["quality"] = estimator.evaluate(w16, x, t)
-    ctx.set_queue_order(mibh.ORDER_EXACT)
-    ctx.compute_forces(theta)  # exact counts of this tree
-    st = stages(lambda: ctx.compute_forces(theta))
-    out["exact_counts"] = {"walk_ms": st["walk"], "mac_prep_ms": st["mac_prep"],
-                           "note": "repeated walks of one tree (the counts of a new tree are not known)"}
+    out["estimator_gain_ms"] = {
+        "vs_morton": out["morton"]["order_and_walk_ms"] - out["estimator"]["order_and_walk_ms"],
+        "vs_exact": out["exact"]["order_and_walk_ms"] - out["estimator"]["order_and_walk_ms"]}
     del ctx
     out["workload"] = f"two_plummers_2x2^21_seeds5_6_sep10_theta{theta:g}"
+    out["timing"] = f"{rounds} alternating rounds x {steps} steps per order, medians"
     return out
 
 
@@ -553,6 +679,7 @@ def main():
         "paper_sections_ms": sections,
         "ms_per_step_stage_events": {"median": float(np.median(step_sums)), "min": step_sums[0]},
         "walk_share": walk_ms / ms_step,
+        "hbm_stages": hbm_stages(stage_ms, n, st["ncells"]),
         "tree": {"ncells": st["ncells"], "ngroups": st["ngroups"], "nleaves": st["nleaves"],
                  "depth": st["depth"]},
         "roofline": {
@@ -589,8 +716,10 @@ def main():
         del p24, m24
         log("[bench] variant: kahan")
         result["variant_kahan"] = bench_variant_kahan(pos, mass, theta, max(3, args.steps // 4), 1)
+        log("[bench] variant: learned estimator training")
+        w16 = train_estimator(pos, mass, theta)
         log("[bench] variant: batched ensemble")
-        result["variant_ensemble"] = bench_variant_ensemble(theta, max(3, args.steps // 4), 1)
+        result["variant_ensemble"], ens_out = bench_variant_ensemble(theta, max(3, args.steps // 4), 1, w16)
         log("[bench] variant: leapfrog driver")
         result["variant_leapfrog"] = bench_variant_leapfrog(n, args.seed, theta, 20)
         log("[bench] variant: block time steps")
@@ -599,11 +728,26 @@ def main():
         log("[bench] variant: neighbour search and SPH density")
         result["variant_neighbors"] = bench_variant_neighbors(pos, mass, 5)
         log("[bench] variant: queue order")
-        result["variant_queue_order"] = bench_variant_queue_order(pos, mass, theta, max(3, args.steps // 4), 1)
+        result["variant_queue_order"] = bench_variant_queue_order(w16, theta, max(3, args.steps // 4))
         log("[bench] variants done")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(pos, mass, theta)
+        if not args.no_variants:
+            log("[bench] cpu baseline: the ensemble")
+            ce = cpu_baseline_ensemble(theta, ens_out)
+            result["cpu_baseline"]["ensemble"] = ce
+            cfg = result["variant_ensemble"]["graph_configs"]
+            result["target_config"] = {
+                "workload": result["variant_ensemble"]["workload"],
+                "plain": {"what": "plain float32 accumulation, Morton queue, graph-replayed batched step",
+                          "particles_per_s": cfg["plain_morton"]["particles_per_s"],
+                          "acc_p99_vs_oracle": ce["acc_p99_vs_oracle"]["plain_morton"],
+                          "pot_p99_vs_oracle": ce["pot_p99_vs_oracle"]["plain_morton"]},
+                "target": {"what": "Kahan accumulation, learned-estimator queue order, graph-replayed batched step",
+                           "particles_per_s": cfg["kahan_estimator"]["particles_per_s"],
+                           "acc_p99_vs_oracle": ce["acc_p99_vs_oracle"]["kahan_estimator"],
+                           "pot_p99_vs_oracle": ce["pot_p99_vs_oracle"]["kahan_estimator"]}}
         log("[bench] cpu baseline done")
     print(json.dumps(result), flush=True)
 

@@ -171,27 +171,42 @@ def cpu_baseline(pos, mass, theta, n_ranges=16, frac=1 / 2):
     }
 
 
-def bench_variant_kahan(pos, mass, theta, steps, warmup):
-    """Same workload with Kahan-compensated accumulation (plain float32 elsewhere)."""
+def bench_variant_kahan(pos, mass, theta, steps, warmup, rounds=3):
+    """Same workload with compensated accumulation: Kahan across the list
+    evaluations (MIBH_KAHAN) and per term (MIBH_KAHAN_TERM), timed in
+    alternation with the plain walk (medians of `rounds` rounds)."""
+    import numpy as np
     import torch
     from paper_1204_2280_amd import mibh
     n = len(mass)
     dev = torch.device("cuda", 0)
     p = torch.from_numpy(pos).to(dev)
     m = torch.from_numpy(mass).to(dev)
-    ctx = mibh.Context(n, device=dev, precision=mibh.KAHAN)
-    for _ in range(warmup):
-        ctx.forces(p, m, theta)
-    ctx.sync()
+    ctxs = {name: mibh.Context(n, device=dev, precision=prec)
+            for name, prec in (("plain", mibh.PLAIN), ("kahan", mibh.KAHAN), ("kahan_term", mibh.KAHAN_TERM))}
+    times = {name: [] for name in ctxs}
+    for name, ctx in ctxs.items():
+        for _ in range(warmup):
+            ctx.forces(p, m, theta)
+        ctx.sync()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(ctx.stream)
-    for _ in range(steps):
-        ctx.forces(p, m, theta)
-    b.record(ctx.stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / steps
-    del ctx
-    return {"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3)}
+    for _ in range(rounds):
+        for name, ctx in ctxs.items():
+            a.record(ctx.stream)
+            for _ in range(steps):
+                ctx.forces(p, m, theta)
+            b.record(ctx.stream)
+            torch.cuda.synchronize()
+            times[name].append(a.elapsed_time(b) / steps)
+    del ctxs
+    out = {}
+    for name, t in times.items():
+        ms = float(np.median(t))
+        out[name] = {"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3)}
+    for name in ("kahan", "kahan_term"):
+        out[name]["cost_vs_plain"] = out[name]["ms_per_step"] / out["plain"]["ms_per_step"] - 1.0
+    out["timing"] = f"{rounds} alternating rounds x {steps} steps per mode, medians"
+    return out
 
 
 def bench_variant_ensemble(theta, steps, warmup, w16, nsys=64, seed=4, rounds=3):
@@ -594,7 +609,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 22)
     ap.add_argument("--theta", type=float, default=0.75)
-    ap.add_argument("--precision", choices=("plain", "kahan"), default="plain")
+    ap.add_argument("--precision", choices=("plain", "kahan", "kahan_term"), default="plain")
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--walk-waves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -621,7 +636,7 @@ def main():
     torch.cuda.set_device(dev)
     p = torch.from_numpy(pos).to(dev)
     m = torch.from_numpy(mass).to(dev)
-    ctx = mibh.Context(n, device=dev, precision=1 if args.precision == "kahan" else 0,
+    ctx = mibh.Context(n, device=dev, precision={"plain": 0, "kahan": 1, "kahan_term": 2}[args.precision],
                        walk_waves=args.walk_waves)
     acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
     pot = torch.empty((n,), dtype=torch.float32, device=dev)

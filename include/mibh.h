@@ -47,7 +47,19 @@ typedef enum {
     MIBH_ENONFINITE = -6   /* a position or mass was NaN/Inf, or a mass was negative */
 } mibh_status;
 
-enum { MIBH_PLAIN = 0, MIBH_KAHAN = 1 };
+/* Per-particle accumulation of the walk's float32 interaction terms.
+ * MIBH_PLAIN: plain float32.  Within one evaluation of the interaction lists
+ * (a full list's flush, or the group's end) each lane sums at most 16 tiles of
+ * terms and the 64 lanes are folded by a six-level tree; a particle's totals
+ * of successive evaluations are then added.
+ * MIBH_KAHAN: the same, with those totals of successive evaluations added with
+ * Kahan compensation (the long sums of a particle with long lists).
+ * MIBH_KAHAN_TERM: every term compensated as it is added to its lane's sum, and
+ * the evaluations' totals as in MIBH_KAHAN (for measurement; the walk runs
+ * 8 group particles per pass instead of 16).
+ * All three walk the same lists: counts are identical, forces differ by
+ * rounding only. */
+enum { MIBH_PLAIN = 0, MIBH_KAHAN = 1, MIBH_KAHAN_TERM = 2 };
 
 /* Parameters of the method and of the walk kernel. */
 typedef struct {
@@ -57,7 +69,7 @@ typedef struct {
                            1 <= ncrit <= group_cap <= 64 (default 64) */
     float eps2;         /* Plummer softening length squared (default 0) */
     float G;            /* gravitational constant (default 1) */
-    int32_t precision;  /* MIBH_PLAIN or MIBH_KAHAN per-particle accumulation (default plain) */
+    int32_t precision;  /* MIBH_PLAIN, MIBH_KAHAN or MIBH_KAHAN_TERM accumulation (default plain) */
     int32_t walk_waves; /* waves of the persistent walk launch; 0 = 4096 (16 per CU of a
                            256-CU MI355X) */
     int32_t pc_cap;     /* per-wave particle-cell list entries (in LDS) before an evaluation

@@ -89,7 +89,7 @@ __global__ void k_set_offsets(SysOffsets o, uint32_t *__restrict__ sys_off) {
 bool params_valid(const mibh_params &p) {
     return p.ncrit >= 1 && p.group_cap >= p.ncrit && p.group_cap <= 64 && p.eps2 >= 0.0f &&
            p.max_systems >= 1 && p.max_systems <= MAX_SYSTEMS &&
-           isfinite(p.eps2) && isfinite(p.G) && (p.precision == MIBH_PLAIN || p.precision == MIBH_KAHAN) &&
+           isfinite(p.eps2) && isfinite(p.G) && (p.precision == MIBH_PLAIN || p.precision == MIBH_KAHAN || p.precision == MIBH_KAHAN_TERM) &&
            p.walk_waves >= 0 && p.walk_waves <= (1 << 20) && p.pc_cap >= 128 && p.pp_cap >= 128 &&
            p.pc_cap <= (int)WALK_PC_LDS && p.pp_cap <= (int)WALK_PP_LDS;
 }

@@ -149,25 +149,36 @@ struct WalkArgs {
     unsigned pc_cap, pp_cap;
 };
 
-// Group particles per evaluation pass: 16 (64 sums per lane), or 8 with
-// Kahan accumulation (32 sums and 32 compensations), so that both variants
-// keep 64 accumulator registers per lane.
-template <bool KAHAN> constexpr int chunk_of() { return KAHAN ? 8 : 16; }
+// Accumulation modes (the library's precision parameter):
+//   0 plain float32;
+//   1 compensated across flushes: within one evaluation of the lists each lane
+//     sums its <= 16 tiles in plain float32 and the lanes are folded by a
+//     six-level tree, and the per-particle totals of successive evaluations
+//     (one per flush of a full list, one at the end of the group) are added
+//     with Kahan compensation: the long sums of a particle are the ones across
+//     evaluations, while those inside one are short and pairwise;
+//   2 compensated per term: every term is added to its lane's sum with Kahan
+//     compensation, and the evaluations' totals as in mode 1.
+// Group particles per evaluation pass: 16 (64 sums per lane), or 8 per term
+// compensated (32 sums and 32 compensations), so that every mode keeps 64
+// accumulator registers per lane.
+template <int PREC> constexpr int chunk_of() { return PREC == 2 ? 8 : 16; }
 // Slot of a lane's reduced value for chunk c in the per-group result array
 // (256 floats: 4 chunks x 64 values, or 8 chunks x 32 values).
-template <bool KAHAN> __device__ __forceinline__ unsigned res_slot(unsigned c, unsigned ln) {
-    return KAHAN ? c * 32u + (ln >> 1) : c * 64u + ln;
+template <int PREC> __device__ __forceinline__ unsigned res_slot(unsigned c, unsigned ln) {
+    return PREC == 2 ? c * 32u + (ln >> 1) : c * 64u + ln;
 }
 constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
 
 // Evaluates `npcl` particle-cell entries and `nppl` particle-particle entries
 // for all `gn` group particles and adds the results into s_res (one value per
 // lane per chunk): one reduction per chunk covers both lists.
-template <bool KAHAN>
+template <int PREC>
 __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, const uint32_t *ppl, unsigned nppl,
                          unsigned gn, float px, float py, float pz, float *s_res, float *s_cmp) {
-    constexpr int CHUNK = chunk_of<KAHAN>();
+    constexpr int CHUNK = chunk_of<PREC>();
     constexpr int NV = 4 * CHUNK;
+    constexpr bool TERM = PREC == 2;
     const unsigned ln = lane64();
     const float eps2 = a.eps2;
     for (unsigned c0 = 0; c0 < gn; c0 += CHUNK) {
@@ -219,7 +230,7 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
                     const float u = RQR * r5;
                     // a = -M R/r^3 + Q R/r^5 - (5/2)(RQR) R/r^7 ; phi = -(M/r + RQR/(2 r^5))
                     const float coef = fmaf(2.5f * u, rinv2, Mr3);
-                    if (KAHAN) {
+                    if (TERM) {
                         add<true>(v[4 * ii + 0], cv[4 * ii + 0], fmaf(QRx, r5, -coef * Rx));
                         add<true>(v[4 * ii + 1], cv[4 * ii + 1], fmaf(QRy, r5, -coef * Ry));
                         add<true>(v[4 * ii + 2], cv[4 * ii + 2], fmaf(QRz, r5, -coef * Rz));
@@ -255,34 +266,34 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
                     rinv = r2 > 0.0f ? rinv : 0.0f;  // self and coincident pairs contribute nothing
                     const float mr = s.w * rinv;
                     const float mr3 = mr * rinv * rinv;
-                    add<KAHAN>(v[4 * ii + 0], cv[4 * ii + 0], mr3 * dx);
-                    add<KAHAN>(v[4 * ii + 1], cv[4 * ii + 1], mr3 * dy);
-                    add<KAHAN>(v[4 * ii + 2], cv[4 * ii + 2], mr3 * dz);
-                    add<KAHAN>(v[4 * ii + 3], cv[4 * ii + 3], -mr);
+                    add<TERM>(v[4 * ii + 0], cv[4 * ii + 0], mr3 * dx);
+                    add<TERM>(v[4 * ii + 1], cv[4 * ii + 1], mr3 * dy);
+                    add<TERM>(v[4 * ii + 2], cv[4 * ii + 2], mr3 * dz);
+                    add<TERM>(v[4 * ii + 3], cv[4 * ii + 3], -mr);
                 }
             }
         }
-        if (KAHAN) {
+        if (TERM) {
 #pragma unroll
             for (int j = 0; j < NV; j++) v[j] = v[j] - cv[j];
         }
         const float r = transpose_reduce<NV>(v);
-        const unsigned slot = res_slot<KAHAN>(c0 / CHUNK, ln);
-        if (KAHAN) add<true>(s_res[slot], s_cmp[slot], r);
+        const unsigned slot = res_slot<PREC>(c0 / CHUNK, ln);
+        if (PREC) add<true>(s_res[slot], s_cmp[slot], r);
         else s_res[slot] += r;
     }
 }
 
 // Evaluates the list's whole 64-entry tiles (all entries if `all`), moves the
 // remaining entries to the front and returns their number.
-template <bool KAHAN, bool PC>
+template <int PREC, bool PC>
 __device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bool all, unsigned gn, float px,
                                float py, float pz, float *s_res, float *s_cmp) {
     const unsigned ne = all ? n : (n & ~63u);
     __syncthreads();  // list entries written by other lanes are visible
     if (ne) {
-        if (PC) evaluate<KAHAN>(a, list, ne, list, 0u, gn, px, py, pz, s_res, s_cmp);
-        else evaluate<KAHAN>(a, list, 0u, list, ne, gn, px, py, pz, s_res, s_cmp);
+        if (PC) evaluate<PREC>(a, list, ne, list, 0u, gn, px, py, pz, s_res, s_cmp);
+        else evaluate<PREC>(a, list, 0u, list, ne, gn, px, py, pz, s_res, s_cmp);
     }
     const unsigned r = n - ne;
     if (r) {
@@ -295,18 +306,18 @@ __device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bo
     return r;
 }
 
-template <bool KAHAN>
+template <int PREC>
 __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
     constexpr unsigned MASK = WALK_LSTACK - 1;
     static_assert((WALK_LSTACK & MASK) == 0 && WALK_LSTACK >= 512, "stack ring must hold one step's pushes");
     __shared__ uint32_t s_stk[WALK_LSTACK];
-    // the Kahan walk's compensations take 768 more bytes of LDS: its
+    // the compensated walks' compensations take 768 more bytes of LDS: their
     // particle-cell list is shorter by as much, so 16 waves still fit a CU
-    constexpr unsigned PC_LDS = KAHAN ? WALK_PC_LDS - 192 : WALK_PC_LDS;
+    constexpr unsigned PC_LDS = PREC ? WALK_PC_LDS - 192 : WALK_PC_LDS;
     __shared__ uint32_t s_pc[PC_LDS];
     __shared__ uint32_t s_pp[WALK_PP_LDS];
     __shared__ float s_res[256];
-    __shared__ float s_cmp[KAHAN ? 256 : 64];
+    __shared__ float s_cmp[PREC ? 256 : 64];
     __shared__ uint32_t s_idx[64];  // group particle evaluated in each lane
     const unsigned ln = lane64();
     uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
@@ -359,7 +370,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
 #pragma unroll
         for (int c = 0; c < 4; c++) {
             s_res[c * 64 + ln] = 0.0f;
-            if (KAHAN) s_cmp[c * 64 + ln] = 0.0f;
+            if (PREC) s_cmp[c * 64 + ln] = 0.0f;
         }
 
         // logical stack = global spill [0, gtop) followed by the LDS ring [sb, st)
@@ -400,7 +411,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             const unsigned long long am = __ballot(accept);
             const unsigned na = (unsigned)__popcll(am);
             if (npc + na > pc_cap)
-                npc = flush_list<KAHAN, true>(a, s_pc, npc, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                npc = flush_list<PREC, true>(a, s_pc, npc, false, ge, p.x, p.y, p.z, s_res, s_cmp);
             if (accept) s_pc[npc + rank_below(am)] = c;
             npc += na;
             tot_pc += na;
@@ -414,7 +425,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
                 const unsigned off = small_excl_scan<5>(rem, &sum);
                 if (sum + 63u <= a.pp_cap) {
                     if (npp + sum > a.pp_cap)
-                        npp = flush_list<KAHAN, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                        npp = flush_list<PREC, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
                     for (unsigned j = 0; j < rem; j++) s_pp[npp + off + j] = src + j;
                     npp += sum;
                     tot_pp += sum;
@@ -426,7 +437,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
                 unsigned sum;
                 const unsigned off = small_excl_scan(take, &sum);
                 if (npp + sum > a.pp_cap)
-                    npp = flush_list<KAHAN, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                    npp = flush_list<PREC, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
                 for (unsigned j = 0; j < take; j++) s_pp[npp + off + j] = src + j;
                 npp += sum;
                 tot_pp += sum;
@@ -461,21 +472,22 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
         }
         if (npc + npp) {
             __syncthreads();  // list entries written by other lanes are visible
-            evaluate<KAHAN>(a, s_pc, npc, s_pp, npp, ge, p.x, p.y, p.z, s_res, s_cmp);
+            evaluate<PREC>(a, s_pc, npc, s_pp, npp, ge, p.x, p.y, p.z, s_res, s_cmp);
         }
 
         // results back to the caller's order
-        constexpr int CHUNK = chunk_of<KAHAN>();
+        constexpr int CHUNK = chunk_of<PREC>();
+        constexpr bool TERM = PREC == 2;
         // value held by this lane: bitrev6(ln) (64 per chunk) or its low five
         // bits (32 per chunk, lanes ln and ln ^ 1 alike: the even one stores)
-        const unsigned idx = KAHAN ? (bitrev6(ln) & 31u) : bitrev6(ln);
+        const unsigned idx = TERM ? (bitrev6(ln) & 31u) : bitrev6(ln);
         const unsigned comp = idx & 3u;
         for (unsigned c = 0; c * CHUNK < ge; c++) {
-            const unsigned pi = c * CHUNK + (idx >> 2) + ((KAHAN && (ln & 1u)) ? 64u : 0u);
+            const unsigned pi = c * CHUNK + (idx >> 2) + ((TERM && (ln & 1u)) ? 64u : 0u);
             if (pi < ge) {
-                const unsigned slot = res_slot<KAHAN>(c, ln);
+                const unsigned slot = res_slot<PREC>(c, ln);
                 float val = s_res[slot];
-                if (KAHAN) val = val - s_cmp[slot];
+                if (PREC) val = val - s_cmp[slot];
                 val *= a.G;
                 const size_t orig = a.perm[gf + s_idx[pi]];
                 if (comp < 3) a.acc[3 * orig + comp] = val;
@@ -512,10 +524,12 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
     a.G = G;
     a.pc_cap = b.pc_cap;
     a.pp_cap = b.pp_cap;
-    if (precision == 1)
-        hipLaunchKernelGGL(k_walk<true>, dim3(b.walk_waves), dim3(64), 0, s, a);
+    if (precision == 2)
+        hipLaunchKernelGGL(k_walk<2>, dim3(b.walk_waves), dim3(64), 0, s, a);
+    else if (precision == 1)
+        hipLaunchKernelGGL(k_walk<1>, dim3(b.walk_waves), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL(k_walk<false>, dim3(b.walk_waves), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_walk<0>, dim3(b.walk_waves), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmibh.so")
 
-PLAIN, KAHAN = 0, 1
+PLAIN, KAHAN, KAHAN_TERM = 0, 1, 2
 EXPORTS = {
     "keys": 0, "perm": 1, "cells": 2, "groups": 3, "counts": 4, "multipoles": 5, "delta": 6,
     "mac": 7, "quad": 8, "spos": 9, "features": 10, "predictions": 11, "queue": 12, "lside": 13,

@@ -176,7 +176,7 @@ def test_kahan_matches_and_is_not_worse(orc):
     T.walk(0.75)
     acc, pot = T.forces()
     errs = {}
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         c = gpu_context(33000, precision=prec)
         g = run_gpu(c, pos, mass, 0.75, exports=("counts",))
         npc, npp = T.counts()
@@ -184,8 +184,9 @@ def test_kahan_matches_and_is_not_worse(orc):
         e = rel_err(g["acc"], acc)
         errs[prec] = (p99(e), float(np.sqrt(np.mean(e ** 2))))
         assert p99(e) <= TOL_P99
-    print(f"[gpu] plain p99/rms {errs[0]}, kahan {errs[1]}", flush=True)
-    assert errs[1][0] <= errs[0][0] * 1.05
+    print(f"[gpu] plain p99/rms {errs[0]}, kahan {errs[1]}, kahan per term {errs[2]}", flush=True)
+    # short lists: the compensated modes differ from plain by rounding noise only
+    assert errs[1][0] <= errs[0][0] * 1.05 and errs[2][0] <= errs[0][0] * 1.05
 
 
 def test_energy_float64(ctx, orc):

@@ -5,8 +5,9 @@ The oracle builds the whole tree (keys, permutation, cells, groups and float64
 multipoles are compared in full) and walks every group: the interaction
 counts of all groups must match bit for bit, and the accelerations and
 potentials of all 4 194 304 particles to 1e-5 at the 99th percentile, for
-theta in {0.5, 0.75, 1.0} with plain float32 accumulation and theta = 0.75
-with Kahan accumulation (same lists, so the same oracle walk).
+theta in {0.5, 0.75, 1.0} with plain float32 accumulation, theta in
+{0.5, 0.75} with Kahan compensation across list evaluations and theta = 0.75
+with Kahan compensation of every term (same lists, so the same oracle walk).
 """
 import numpy as np
 import pytest
@@ -40,7 +41,7 @@ def _oracle_walk(T, cache, theta):
     return cache[theta]
 
 
-@pytest.mark.parametrize("theta,precision", [(0.75, 0), (0.75, 1), (0.5, 0), (1.0, 0)])
+@pytest.mark.parametrize("theta,precision", [(0.75, 0), (0.75, 1), (0.75, 2), (0.5, 0), (0.5, 1), (1.0, 0)])
 def test_full_size_parity(full, theta, precision):
     pos, mass, T, ctx0, cache = full
     ctx = ctx0 if precision == 0 else gpu_context(N, precision=precision)

@@ -500,16 +500,68 @@ def bench_variant_block_steps(n, seed, theta, shared_ms):
     t3, lev, st3 = run(3)
     steady = (t3 - t1) / 2
     hist = torch.bincount(lev.to(torch.int64), minlength=5).cpu().tolist()
+    ticks = block_tick_walks(ctx, P, M, lev, theta)
     del ctx
     upd = (st3["active_updates"] - st1["active_updates"]) / 2
     out = {"workload": f"plummer_n{n}_seed{seed}_theta{theta:g}_eps2{1e-4:g}_dtmax{1 / 16:g}_levels0-4",
            "schedule_3_steps": st3, "levels_last_step": hist, "ms_one_step_with_initial_forces": t1,
            "ms_three_steps": t3, "ms_per_dt_max_steady": steady,
-           "active_fraction": upd / (n * 16), "particle_updates_per_s": upd / (steady * 1e-3)}
+           "active_fraction": upd / (n * 16), "particle_updates_per_s": upd / (steady * 1e-3),
+           "tick_walks": ticks}
     if shared_ms:
         out["ms_shared_16_smallest_steps"] = 16 * shared_ms
         out["speedup_vs_shared_smallest_steps"] = 16 * shared_ms / steady
     return out
+
+def block_tick_walks(ctx, P, M, levels, theta, reps=5):
+    """The active walks of block time steps, one per due set that the last
+    step's levels give (level >= r is due at the ticks aligned to dt_max/2^r):
+    the walk's time (stage events, median of reps) against a full walk of the
+    same tree, beside the shares of the particles evaluated and of the visited
+    groups' work, work = particles x (n_pc + n_pp): the groups' whole lists are
+    built (traversal) for every visited group, and only the active particles
+    are evaluated."""
+    import numpy as np
+    import torch
+    from paper_1204_2280_amd import mibh
+    ctx.forces(P, M, theta)
+    ctx.sync()
+    counts = ctx.export("counts").view(torch.int32).reshape(-1, 2).cpu().numpy().astype(np.int64)
+    grp = mibh.Decoded.groups(ctx.export("groups"))
+    perm = ctx.export("perm").cpu().numpy().view(np.uint32).astype(np.int64)
+    lists = counts[:, 0] + counts[:, 1]
+    gn = np.asarray(grp["count"], np.int64)
+    gfirst = np.asarray(grp["first"], np.int64)
+    total = float(np.sum(gn * lists))
+    lev_sorted = levels.cpu().numpy()[perm]
+    acc = torch.empty((P.shape[0], 3), dtype=torch.float32, device=P.device)
+    pot = torch.empty((P.shape[0],), dtype=torch.float32, device=P.device)
+
+    def walk_ms(fn):
+        fn()
+        ctx.sync()
+        ctx.profile_begin(reps)
+        for _ in range(reps):
+            fn()
+        return float(np.median([r["walk"] for r in ctx.profile_read()]))
+
+    full_ms = walk_ms(lambda: ctx.compute_forces(theta, acc, pot))
+    out = {"full_walk_ms": full_ms, "due_sets": []}
+    for r in sorted(set(int(x) for x in np.unique(lev_sorted)), reverse=True):
+        due_sorted = (lev_sorted >= r).astype(np.int64)
+        csum = np.concatenate([[0], np.cumsum(due_sorted)])
+        active_in_group = csum[gfirst + gn] - csum[gfirst]
+        visited = active_in_group > 0
+        mask = (levels >= r).to(torch.uint8)
+        ms = walk_ms(lambda: ctx.compute_forces_active(theta, mask, acc, pot))
+        out["due_sets"].append({
+            "levels_due": f">= {r}", "particles_share": float(due_sorted.mean()),
+            "groups_share": float(visited.mean()),
+            "visited_groups_work_share": float(np.sum((gn * lists)[visited]) / total),
+            "evaluated_work_share": float(np.sum(active_in_group * lists) / total),
+            "walk_ms": ms, "walk_share": ms / full_ms})
+    return out
+
 
 def bench_variant_neighbors(pos, mass, steps):
     """Neighbour search and SPH density on the benchmark sphere (tree of the

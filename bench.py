@@ -500,27 +500,47 @@ def bench_variant_block_steps(n, seed, theta, shared_ms):
     t3, lev, st3 = run(3)
     steady = (t3 - t1) / 2
     hist = torch.bincount(lev.to(torch.int64), minlength=5).cpu().tolist()
-    ticks = block_tick_walks(ctx, P, M, lev, theta)
+    ticks = block_tick_walks(ctx, P, V, M, lev, theta, args[1] / 16)
+    # the same steps rebuilding the tree before every walk (no refits)
+    args_rb = args
+    def run_rb(nbig):
+        P.copy_(torch.from_numpy(pos))
+        V.copy_(torch.from_numpy(vel))
+        ctx.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(ctx.stream)
+        _, _, _, st, _ = ctx.block_run(P, V, M, *args_rb, nbig, rebuild_tol=-1.0, log=False)
+        b.record(ctx.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b), st
+    run_rb(1)
+    r1, _ = run_rb(1)
+    r3, rst3 = run_rb(3)
+    steady_rb = (r3 - r1) / 2
     del ctx
     upd = (st3["active_updates"] - st1["active_updates"]) / 2
     out = {"workload": f"plummer_n{n}_seed{seed}_theta{theta:g}_eps2{1e-4:g}_dtmax{1 / 16:g}_levels0-4",
            "schedule_3_steps": st3, "levels_last_step": hist, "ms_one_step_with_initial_forces": t1,
            "ms_three_steps": t3, "ms_per_dt_max_steady": steady,
            "active_fraction": upd / (n * 16), "particle_updates_per_s": upd / (steady * 1e-3),
-           "tick_walks": ticks}
+           "tick_walks": ticks,
+           "rebuild_before_every_walk": {"schedule_3_steps": rst3, "ms_per_dt_max_steady": steady_rb}}
     if shared_ms:
         out["ms_shared_16_smallest_steps"] = 16 * shared_ms
         out["speedup_vs_shared_smallest_steps"] = 16 * shared_ms / steady
+        out["rebuild_before_every_walk"]["speedup_vs_shared_smallest_steps"] = 16 * shared_ms / steady_rb
     return out
 
-def block_tick_walks(ctx, P, M, levels, theta, reps=5):
+def block_tick_walks(ctx, P, V, M, levels, theta, dt_min, reps=5):
     """The active walks of block time steps, one per due set that the last
     step's levels give (level >= r is due at the ticks aligned to dt_max/2^r):
     the walk's time (stage events, median of reps) against a full walk of the
     same tree, beside the shares of the particles evaluated and of the visited
     groups' work, work = particles x (n_pc + n_pp): the groups' whole lists are
     built (traversal) for every visited group, and only the active particles
-    are evaluated."""
+    are evaluated.  Then the finest due set's walk on trees refitted after the
+    particles drifted k ticks (k = 1, 2, 4) from the build, with its visited
+    groups' interaction counts against the fresh tree's."""
     import numpy as np
     import torch
     from paper_1204_2280_amd import mibh
@@ -560,6 +580,29 @@ def block_tick_walks(ctx, P, M, levels, theta, reps=5):
             "visited_groups_work_share": float(np.sum((gn * lists)[visited]) / total),
             "evaluated_work_share": float(np.sum(active_in_group * lists) / total),
             "walk_ms": ms, "walk_share": ms / full_ms})
+    # refitted trees: the finest due set after k ticks of drift
+    r = int(lev_sorted.max())
+    mask = (levels >= r).to(torch.uint8)
+    fresh_work = None
+    P0 = P.clone()
+    out["refit_drift"] = []
+    for k in (0, 1, 2, 4):
+        if k == 0:
+            ctx.build_tree(P0, M)
+        else:
+            P.copy_(P0 + (k * dt_min) * V)
+            ctx.refit(P, M)
+        ctx.compute_multipoles()
+        ms = walk_ms(lambda: ctx.compute_forces_active(theta, mask, acc, pot))
+        c = ctx.export("counts").view(torch.int32).reshape(-1, 2).cpu().numpy().astype(np.int64)
+        vis = np.zeros(len(gn), bool)
+        csum = np.concatenate([[0], np.cumsum((lev_sorted >= r).astype(np.int64))])
+        vis[(csum[gfirst + gn] - csum[gfirst]) > 0] = True
+        work = float(np.sum((gn * (c[:, 0] + c[:, 1]))[vis]))
+        if fresh_work is None:
+            fresh_work = work
+        out["refit_drift"].append({"ticks_since_build": k, "walk_ms": ms, "visited_work_vs_fresh": work / fresh_work})
+    P.copy_(P0)
     return out
 
 

@@ -975,6 +975,9 @@ __global__ __launch_bounds__(256) void k_multipole_leaves(
 // the cell code holds many registers (two waves per SIMD), so small
 // workgroups spread a level's internal cells over more compute units.
 constexpr unsigned MP_INTERNAL_THREADS = 64;
+#ifndef MP_INTERNAL_GRID
+#define MP_INTERNAL_GRID 1024u  // workgroups per level launch (grid-stride over the level's cells; 8192 and 256 were slower)
+#endif
 
 __global__ __launch_bounds__(MP_INTERNAL_THREADS) void k_multipole_internal(
     int lev, const Header *__restrict__ hdr, const SysCube *__restrict__ cube, const uint4 *__restrict__ topo,
@@ -1053,7 +1056,7 @@ hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_multipole_leaves, dim3(grid), dim3(256), 0, s, b.hdr, b.cube, b.topo, b.spos, keys, b.mp,
                        b.delta, b.cbox, b.lside, b.cmac, b.ceval, b.cap_cells);
     // level KEY_LEVELS holds leaves only
-    const unsigned igrid = min((b.cap_cells + MP_INTERNAL_THREADS - 1u) / MP_INTERNAL_THREADS, 8192u);
+    const unsigned igrid = min((b.cap_cells + MP_INTERNAL_THREADS - 1u) / MP_INTERNAL_THREADS, MP_INTERNAL_GRID);
     for (int lev = KEY_LEVELS - 1; lev >= 0; lev--)
         hipLaunchKernelGGL(k_multipole_internal, dim3(igrid), dim3(MP_INTERNAL_THREADS), 0, s, lev, b.hdr, b.cube,
                            b.topo, keys, b.mp, b.delta, b.cbox, b.lside, b.cmac, b.ceval, b.cap_cells);

@@ -78,6 +78,17 @@ typedef struct {
                            128 <= pp_cap <= 512 (default 512) */
     int32_t max_systems; /* most independent systems one batched build may hold,
                             1 <= max_systems <= 256 (default 1) */
+    int32_t anchor_up;  /* 0: every group's traversal starts at its root.
+                           1..4 (default 3): the groups below each ancestor cell
+                           anchor_up levels above them share one traversal with the
+                           ancestor's particle box: the cells it accepts are accepted by
+                           every such group, the cells it surely opens (its box's
+                           farthest point inside the opening radius) are opened by every
+                           such group, and each group traverses only the rest.  Same
+                           lists and counts as 0, summed in another order, by every walk
+                           (any queue order; active walks build the lists of their
+                           groups' anchors only).  Adds 8 bytes per particle, 16 per cell and a pool of
+                           (16 >> (anchor_up - 1)) words per particle to the workspace. */
 } mibh_params;
 
 /* Fills the defaults listed above. */
@@ -164,7 +175,8 @@ mibh_status mibh_forces(mibh_ctx *ctx, const float *d_pos, const float *d_mass, 
 /* The force step for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation.
  * Same result as mibh_forces with default parameters (ncrit 16, groups of
- * <= 64, eps2 0, G 1, plain float32 accumulation), bit for bit, for
+ * <= 64, eps2 0, G 1, plain float32 accumulation) except anchor_up = 0 (every
+ * group's traversal starts at the root; no anchor buffers), bit for bit, for
  * 1 <= n <= mibh_static_n_max() (32768) particles; larger n gives EINVAL.
  * Inputs and outputs are the caller's device arrays, laid out as for
  * mibh_forces; work is enqueued on `stream` (a hipStream_t, NULL: the null

@@ -91,7 +91,7 @@ bool params_valid(const mibh_params &p) {
            p.max_systems >= 1 && p.max_systems <= MAX_SYSTEMS &&
            isfinite(p.eps2) && isfinite(p.G) && (p.precision == MIBH_PLAIN || p.precision == MIBH_KAHAN || p.precision == MIBH_KAHAN_TERM) &&
            p.walk_waves >= 0 && p.walk_waves <= (1 << 20) && p.pc_cap >= 128 && p.pp_cap >= 128 &&
-           p.pc_cap <= (int)WALK_PC_LDS && p.pp_cap <= (int)WALK_PP_LDS;
+           p.pc_cap <= (int)WALK_PC_LDS && p.pp_cap <= (int)WALK_PP_LDS && p.anchor_up >= 0 && p.anchor_up <= 4;
 }
 
 // Assigns every buffer of the layout from `base` (nullptr: sizing only) and
@@ -147,6 +147,15 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.gref = (uint32_t *)take(4 * n);
     t.bsum = (unsigned long long *)take(8 * 4);
     t.qorder = (uint32_t *)take(4 * n);
+    const bool shared_walk = p.anchor_up > 0;
+    t.anchor = shared_walk ? (uint32_t *)take(4 * n) : nullptr;
+    t.alist = shared_walk ? (uint32_t *)take(4 * n) : nullptr;
+    t.arec = shared_walk ? (uint4 *)take(16 * cap_cells) : nullptr;
+    const size_t pool_words =
+        shared_walk ? std::min<size_t>((size_t)(PREFIX_POOL_WORDS_1 >> (p.anchor_up - 1)) * n, 0xffffffffull) : 0;
+    t.pool = shared_walk ? (uint32_t *)take(4 * pool_words) : nullptr;
+    t.pscr = shared_walk ? (uint32_t *)take(4 * (size_t)PREFIX_SCRATCH * waves) : nullptr;
+    t.pool_cap = pool_words;
     t.ohist = (uint32_t *)take(4 * ORDER_BUCKETS * ORDER_BLOCKS);
     t.epart = (double *)take(8 * 2 * ENERGY_BLOCKS + 16);
     t.cap_cells = (unsigned)cap_cells;
@@ -211,6 +220,7 @@ void mibh_default_params(mibh_params *p) {
     p->pc_cap = (int32_t)WALK_PC_LDS;
     p->pp_cap = (int32_t)WALK_PP_LDS;
     p->max_systems = 1;
+    p->anchor_up = 3;
 }
 
 size_t mibh_workspace_bytes(int64_t n_max, const mibh_params *pp) {
@@ -383,7 +393,8 @@ static mibh_status forces_impl(mibh_ctx *ctx, float theta, const uint8_t *d_acti
     if ((st = mark(ctx, MIBH_STAGE_MACPREP))) return st;
     HIP_TRY(launch_walk(ctx->b, (unsigned)ctx->n, (unsigned)ctx->nsys, ctx->p.eps2, ctx->p.G, ctx->p.precision,
                         mode == MIBH_ORDER_MORTON ? nullptr : ctx->b.qorder,
-                        d_active ? ctx->b.ohist + ORDER_BLOCKS : nullptr, d_active, d_acc, d_pot, ctx->stream),
+                        d_active ? ctx->b.ohist + ORDER_BLOCKS : nullptr, d_active, d_acc, d_pot, ctx->p.anchor_up,
+                        ctx->stream),
             "walk");
     ctx->last_order = mode;
     if ((st = mark(ctx, MIBH_STAGE_WALK))) return st;
@@ -1010,6 +1021,7 @@ mibh_status mibh_forces_static(const float *d_pos, const float *d_mass, int64_t 
     if (!slot.ready) {
         mibh_default_params(&c->p);
         c->p.walk_waves = STATIC_WALK_WAVES;
+        c->p.anchor_up = 0;  // the walk from the root: no anchor buffers in the static workspace
         const size_t need = layout(STATIC_N_MAX, c->p, nullptr, nullptr);
         if (need > STATIC_BYTES)
             return fail(MIBH_ENOMEM, "static workspace too small: %zu < %zu bytes", STATIC_BYTES, need);

@@ -60,6 +60,12 @@ struct Header {
     // sharing a line with the fields above, which every wave reads, made the
     // walk 1.8 times slower.
     alignas(256) unsigned walk_head[8 * 64];
+    // Shared-prefix walk: heads of the anchor pass's queues (as walk_head), then
+    // the allocation head of the anchor-list pool and the number of anchors.
+    alignas(256) unsigned prefix_head[8 * 64];
+    alignas(256) unsigned long long pool_head;
+    unsigned anchor_count;
+    unsigned pool_pad[61];
 };
 
 // Group queues of the persistent walks.  gfx950 deals the workgroups of a
@@ -101,6 +107,19 @@ constexpr int ORDER_BLOCKS = 256;
 
 // Walk: LDS capacities per wave (one wave per workgroup).
 constexpr unsigned WALK_LSTACK = 512;   // cell stack in LDS (spills to the global stack)
+// Shared-prefix walk: per-wave scratch for an anchor cell's lists: the cells it
+// accepts (F), then the cells left for each group, raw and sorted by level (S).
+constexpr unsigned PREFIX_F_CAP = 3072;
+constexpr unsigned PREFIX_S_CAP = 512;  // a seed of <= 512 cells keeps the stack within STACK_CAP
+constexpr unsigned PREFIX_SCRATCH = PREFIX_F_CAP + 2 * PREFIX_S_CAP;
+// Pool words per particle for all anchors' lists: 16 >> (anchor_up - 1), as
+// anchors get fewer and larger with their height (at N = 2^22 in a Plummer
+// sphere the lists take about 0.8 words per particle at height 3); capped at
+// 2^32 - 1 words, the reach of a 32-bit offset.  Anchors that find no room
+// leave their groups to walk from the root.
+constexpr unsigned PREFIX_POOL_WORDS_1 = 16;
+constexpr unsigned PREFIX_STEP = 4;     // stack cells per lane in one step of an anchor's traversal
+constexpr unsigned PREFIX_RING = 4096;  // LDS stack ring of the anchor-list pass
 constexpr unsigned WALK_PC_LDS = 1024;  // particle-cell list
 constexpr unsigned WALK_PP_LDS = 512;   // particle-particle list
 
@@ -138,6 +157,13 @@ struct Buffers {
     uint32_t *gref;         // block time steps: work of a group at its first walk after a build (0: none)
     unsigned long long *bsum;  // block time steps: [0] work now, [1] reference work, [2] due particles
     uint32_t *qorder;       // walk queue: groups in processing order (work-ordered modes)
+    uint32_t *anchor;       // shared-prefix walk: anchor cell of each group
+    uint32_t *alist;        // shared-prefix walk: the anchor cells, each once
+    uint4 *arec;            // shared-prefix walk, per cell: pool offset, |F|, |S|, 1 if the lists are valid
+                            // (2 while claimed, before the lists are built)
+    uint32_t *pool;         // shared-prefix walk: the anchors' F and S lists
+    uint32_t *pscr;         // shared-prefix walk: PREFIX_SCRATCH words per walk wave
+    unsigned long long pool_cap;  // words of the pool
     uint32_t *ohist;        // [ORDER_BUCKETS][ORDER_BLOCKS] bucket counts of the queue order
     double *epart;          // energy partials [ENERGY_BLOCKS][2]
     unsigned cap_cells, n_max, ntiles_max, nblk_max;
@@ -169,9 +195,10 @@ hipError_t launch_multipoles(const Buffers &b, unsigned nsys, hipStream_t s);
 hipError_t launch_mac_prep(const Buffers &b, unsigned nsys, double theta, hipStream_t s);
 // order: the queue (NULL: groups in Morton order); qlen: device count of queue
 // entries to walk (NULL: every group)
+// anchor_up > 0: groups share the traversal of their ancestor anchor_up levels up
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
                        const uint32_t *order, const uint32_t *qlen, const uint8_t *active, float *acc, float *pot,
-                       hipStream_t s);
+                       int anchor_up, hipStream_t s);
 hipError_t launch_features(const Buffers &b, float theta, float *feat, hipStream_t s);
 hipError_t launch_mlp_forward(const void *w16, const float *x, unsigned rows, const Header *hdr, float *y,
                               hipStream_t s);

@@ -1072,8 +1072,14 @@ __global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr, cons
 #pragma clang fp contract(off)
     if (hdr->flags & FLAG_CELLCAP) return;
     const unsigned nc = min(hdr->ncells, cap_cells);
-    if (blockIdx.x == 0 && threadIdx.x < WALK_QUEUES)
-        hdr->walk_head[QUEUE_STRIDE * threadIdx.x] = 0;  // queues of the walk that follows
+    if (blockIdx.x == 0 && threadIdx.x < WALK_QUEUES) {  // queues of the walk that follows
+        hdr->walk_head[QUEUE_STRIDE * threadIdx.x] = 0;
+        hdr->prefix_head[QUEUE_STRIDE * threadIdx.x] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr->pool_head = 0;
+        hdr->anchor_count = 0;
+    }
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
         const double ro = lside[c] / theta + delta[c];
         cmac[c].w = (float)(ro * ro);

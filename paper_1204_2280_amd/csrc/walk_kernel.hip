@@ -118,6 +118,20 @@ __device__ __forceinline__ bool mac_accept(float3 bmin, float3 bmax, float4 m) {
     return d2 > m.w;
 }
 
+// The opening test's distance taken to the box's farthest point instead of its
+// nearest: d_a = max(max(bmax_a - c_a, c_a - bmin_a), 0), same operation order.
+// For any box B' inside [bmin, bmax] each rounded step of the nearest-point
+// distance of B' is at most the same step here, so d2(B') <= far_d2: a cell with
+// far_d2 <= r_open^2 is opened for every group inside the box.
+__device__ __forceinline__ float far_d2(float3 bmin, float3 bmax, float4 m) {
+#pragma clang fp contract(off)
+    float u, v, t;
+    u = bmax.x - m.x; v = m.x - bmin.x; t = u > v ? u : v; const float dx = t > 0.0f ? t : 0.0f;
+    u = bmax.y - m.y; v = m.y - bmin.y; t = u > v ? u : v; const float dy = t > 0.0f ? t : 0.0f;
+    u = bmax.z - m.z; v = m.z - bmin.z; t = u > v ? u : v; const float dz = t > 0.0f ? t : 0.0f;
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
 template <bool KAHAN>
 __device__ __forceinline__ void add(float &s, float &c, float x) {
     if (KAHAN) {
@@ -147,6 +161,11 @@ struct WalkArgs {
     float *acc, *pot;
     float eps2, G;
     unsigned pc_cap, pp_cap;
+    // shared-prefix walk
+    const float *cbox;       // cells' particle boxes
+    const uint32_t *anchor;  // anchor cell of each group
+    const uint4 *arec;       // per anchor cell: pool offset, |F|, |S|, valid
+    const uint32_t *pool;    // the anchors' lists
 };
 
 // Accumulation modes (the library's precision parameter):
@@ -306,7 +325,7 @@ __device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bo
     return r;
 }
 
-template <int PREC>
+template <int PREC, bool SHARED>
 __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
     constexpr unsigned MASK = WALK_LSTACK - 1;
     static_assert((WALK_LSTACK & MASK) == 0 && WALK_LSTACK >= 512, "stack ring must hold one step's pushes");
@@ -374,16 +393,43 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
         }
 
         // logical stack = global spill [0, gtop) followed by the LDS ring [sb, st)
-        // The root is an ancestor of every group, so the walk always opens it:
-        // its children (the root itself when it is a leaf) start the stack, in
-        // the order its opening would push them.
-        const uint4 tr = a.topo[root];
-        const unsigned rn = uniform(tr.w & 255u);
-        unsigned sb = 0, st = rn ? rn : 1u, gtop = 0;
+        unsigned sb = 0, st = 0, gtop = 0;
         unsigned npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
         bool overflow = false;
-        const unsigned first = rn ? tr.z + min(ln, rn - 1) : root;
-        if (ln < st) s_stk[ln] = first;
+        bool seeded = false;
+        if (SHARED) {
+            // the lists shared by the groups below this group's anchor cell: its
+            // accepted cells go into the particle-cell list as they are, and the
+            // stack starts with the cells left (sorted by level, shallowest at the
+            // bottom, so that stack levels never decrease towards the top)
+            const uint4 rec = a.arec[uniform(a.anchor[g])];
+            seeded = uniform(rec.w) == 1u;
+            if (seeded) {
+                const unsigned off = uniform(rec.x), nf = uniform(rec.y), ns = uniform(rec.z);
+                for (unsigned i = ln; i < ns; i += 64) gstk[i] = a.pool[off + nf + i];
+                gtop = ns;
+                for (unsigned k0 = 0; k0 < nf; k0 += 64) {
+                    const unsigned cnt = min(64u, nf - k0);
+                    if (npc + cnt > pc_cap)
+                        npc = flush_list<PREC, true>(a, s_pc, npc, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                    const unsigned v = ln < cnt ? a.pool[off + k0 + ln] : 0u;
+                    if (ln < cnt) s_pc[npc + ln] = v;
+                    npc += cnt;
+                    tot_pc += cnt;
+                }
+            }
+        }
+        if (!seeded) {
+            // The root is an ancestor of every group, so the walk always opens it:
+            // its children (the root itself when it is a leaf) start the stack, in
+            // the order its opening would push them.
+            const uint4 tr = a.topo[root];
+            const unsigned rn = uniform(tr.w & 255u);
+            st = rn ? rn : 1u;
+            const unsigned first = rn ? tr.z + min(ln, rn - 1) : root;
+            if (ln < st) s_stk[ln] = first;
+        }
+        __threadfence_block();
         __syncthreads();
         while (st != sb || gtop > 0) {
             if (st == sb) {  // LDS part empty: refill from the top of the global spill
@@ -498,11 +544,232 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
     }
 }
 
+// --------------------------------------------------------------------------
+// Shared-prefix walk: the groups below one anchor cell A (the ancestor `up`
+// levels above each group) share the part of their traversals that A's
+// particle box decides for all of them.  From the root, with A's box:
+//   * a cell that is an ancestor-or-self of A, or whose opening radius reaches
+//     the farthest point of A's box, is opened by every group inside A: its
+//     children are visited, and a leaf among them is left to each group (it
+//     lands in the group's particle-particle list);
+//   * a cell A's box accepts (the group MAC with A's box) is accepted by every
+//     group inside A: the group's box lies inside A's, so its rounded distance
+//     is no smaller; such a cell is never an ancestor of a group (it would
+//     contain A or lie inside it);
+//   * any other cell is left to each group.
+// Each group then starts with the accepted cells (F) in its particle-cell list
+// and the cells left (S) on its stack and walks on as usual: the same cells
+// are accepted and opened as in a walk from the root, in another order.
+// --------------------------------------------------------------------------
+
+// Anchor of every group: the cell at level max(level - up, 0) that holds the
+// group's first particle (cells of one level are numbered in particle order).
+// The anchor's record is cleared here; k_walk_claim then lists each anchor once.
+__global__ __launch_bounds__(256) void k_walk_anchor(const Header *__restrict__ hdr, const uint2 *__restrict__ groups,
+                                                     const uint4 *__restrict__ topo, int up,
+                                                     uint32_t *__restrict__ anchor, uint4 *__restrict__ arec) {
+    if (hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
+    const unsigned ng = hdr->ngroups;
+    for (unsigned g = blockIdx.x * 256u + threadIdx.x; g < ng; g += gridDim.x * 256u) {
+        const uint2 gr = groups[g];
+        const int glev = (int)((gr.y >> 8) & 255u);
+        const int lev = glev > up ? glev - up : 0;
+        unsigned lo = hdr->lvl_begin[lev], hi = hdr->lvl_begin[lev + 1];  // topo[lo].x <= gr.x
+        while (hi - lo > 1) {
+            const unsigned mid = lo + (hi - lo) / 2;
+            if (topo[mid].x <= gr.x) lo = mid; else hi = mid;
+        }
+        anchor[g] = lo;
+        arec[lo] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+// Anchor list: the anchors of the groups the walk visits (every group, or the
+// queue's first *qlen entries), each once, appended by the one group that claims
+// it (a compare-and-swap of the record's valid word from 0 to 2).  Only entries
+// whose anchor differs from the previous entry's try: in Morton order an
+// anchor's groups are contiguous unless groups of deeper levels sit between
+// them, so few entries compete.
+__global__ __launch_bounds__(256) void k_walk_claim(const Header *__restrict__ hdr,
+                                                    const uint32_t *__restrict__ anchor, const uint32_t *order,
+                                                    const uint32_t *qlen, uint4 *__restrict__ arec,
+                                                    uint32_t *__restrict__ alist, unsigned *__restrict__ acount) {
+    if (hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
+    const unsigned ng = hdr->ngroups;
+    const unsigned nq = qlen ? min(*qlen, ng) : ng;
+    for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < nq; i += gridDim.x * 256u) {
+        const unsigned A = anchor[order ? order[i] : i];
+        const bool starts = i == 0 || anchor[order ? order[i - 1] : i - 1] != A;
+        if (starts && atomicCAS(&arec[A].w, 0u, 2u) == 0u) alist[atomicAdd(acount, 1u)] = A;
+    }
+}
+
+// F and S of anchor cell A into this wave's scratch (F at pf, S sorted by level
+// at pf + PREFIX_F_CAP + PREFIX_S_CAP).  False when a list outgrows its room or
+// the stack its bound (the groups then walk from the root).  A step takes up to
+// PREFIX_STEP cells per lane off the stack: the pass is bound by the dependent
+// round trips of its longest traversal, not by its arithmetic.
+__device__ bool anchor_lists(const WalkArgs &a, unsigned A, uint32_t *s_stk, uint32_t *gstk, uint32_t *pf,
+                             unsigned *nf_out, unsigned *ns_out) {
+    constexpr unsigned K = PREFIX_STEP, RING = PREFIX_RING, MASK = RING - 1;
+    static_assert((RING & MASK) == 0 && RING >= 2 * 64 * 8 * K, "ring must hold one step's pushes");
+    const unsigned ln = lane64();
+    uint32_t *praw = pf + PREFIX_F_CAP, *pseed = praw + PREFIX_S_CAP;
+    const uint4 ta = a.topo[A];
+    const unsigned af = uniform(ta.x), alev = uniform((ta.w >> 8) & 255u), root = uniform(ta.w >> 16);
+    const float *cb = a.cbox + 6 * (size_t)A;
+    const float3 bmin = make_float3(cb[0], cb[1], cb[2]), bmax = make_float3(cb[3], cb[4], cb[5]);
+    const uint4 tr = a.topo[root];
+    const unsigned rn = uniform(tr.w & 255u);
+    unsigned sb = 0, st = rn ? rn : 1u, gtop = 0, nf = 0, ns = 0;
+    bool ok = true;
+    const unsigned first = rn ? tr.z + min(ln, rn - 1) : root;
+    if (ln < st) s_stk[ln] = first;
+    __syncthreads();
+    while (st != sb || gtop > 0) {
+        if (st == sb) {  // LDS part empty: refill from the top of the global spill
+            const unsigned k = min(gtop, RING / 2);
+            __threadfence_block();
+            for (unsigned i = ln; i < k; i += 64) s_stk[(sb - k + i) & MASK] = gstk[gtop - k + i];
+            sb -= k;
+            gtop -= k;
+            __syncthreads();
+        }
+        const unsigned m = min(st - sb, 64u * K);
+        unsigned c[K];
+        uint4 t[K];
+        float4 mc[K];
+#pragma unroll
+        for (unsigned k = 0; k < K; k++) {
+            const unsigned i = k * 64u + ln;
+            c[k] = i < m ? s_stk[(st - m + i) & MASK] : 0u;
+        }
+#pragma unroll
+        for (unsigned k = 0; k < K; k++) {
+            t[k] = a.topo[c[k]];
+            mc[k] = a.cmac[c[k]];
+        }
+        st -= m;
+        unsigned nc[K], nsum = 0;
+#pragma unroll
+        for (unsigned k = 0; k < K; k++) {
+            const bool valid = k * 64u + ln < m;
+            const unsigned lvl = (t[k].w >> 8) & 255u, nch = t[k].w & 255u;
+            const bool anc = t[k].x <= af && af < t[k].x + t[k].y && lvl <= alev;
+            const bool open = valid && (anc || !(far_d2(bmin, bmax, mc[k]) > mc[k].w));
+            const bool accept = valid && !open && mac_accept(bmin, bmax, mc[k]);
+            const bool left = valid && !accept && (!open || nch == 0);
+            const unsigned long long am = __ballot(accept);
+            const unsigned na = (unsigned)__popcll(am);
+            const unsigned long long lm = __ballot(left);
+            const unsigned nl = (unsigned)__popcll(lm);
+            if (nf + na > PREFIX_F_CAP || ns + nl > PREFIX_S_CAP) ok = false;
+            if (ok && accept) pf[nf + rank_below(am)] = c[k];
+            if (ok && left) praw[ns + rank_below(lm)] = c[k];
+            nf += na;
+            ns += nl;
+            nc[k] = open ? nch : 0u;
+            unsigned tk;
+            const unsigned o = small_excl_scan(nc[k], &tk);
+            nc[k] |= (nsum + o) << 8;  // this lane's first push slot above st, with its count
+            nsum += tk;
+        }
+        if (!ok) break;
+        const unsigned used = st - sb;
+        if (used + nsum > RING) {  // spill the bottom of the LDS ring
+            const unsigned need = used + nsum - RING;
+            const unsigned sp = min(used, max(need, RING / 2));
+            if (gtop + sp > STACK_CAP) {
+                ok = false;
+                break;
+            }
+            for (unsigned i = ln; i < sp; i += 64) gstk[gtop + i] = s_stk[(sb + i) & MASK];
+            sb += sp;
+            gtop += sp;
+            __syncthreads();
+        }
+#pragma unroll
+        for (unsigned k = 0; k < K; k++) {
+            const unsigned cnt = nc[k] & 255u, off = nc[k] >> 8;
+            for (unsigned j = 0; j < cnt; j++) s_stk[(st + off + j) & MASK] = t[k].z + j;
+        }
+        st += nsum;
+        __syncthreads();
+    }
+    __threadfence_block();
+    if (ok) {  // S by level, shallowest first: a counting pass over the levels
+        unsigned cell[PREFIX_S_CAP / 64], lv[PREFIX_S_CAP / 64];
+#pragma unroll
+        for (unsigned k = 0; k < PREFIX_S_CAP / 64; k++) {
+            const unsigned i = k * 64 + ln;
+            cell[k] = i < ns ? praw[i] : 0u;
+            lv[k] = i < ns ? (a.topo[cell[k]].w >> 8) & 255u : 255u;
+        }
+        unsigned pos = 0;
+        for (unsigned l = 0; l <= (unsigned)KEY_LEVELS; l++) {
+#pragma unroll
+            for (unsigned k = 0; k < PREFIX_S_CAP / 64; k++) {
+                const bool h = lv[k] == l;
+                const unsigned long long hm = __ballot(h);
+                if (h) pseed[pos + rank_below(hm)] = cell[k];
+                pos += (unsigned)__popcll(hm);
+            }
+        }
+        __threadfence_block();
+    }
+    *nf_out = nf;
+    *ns_out = ns;
+    return ok;
+}
+
+// One pass over the anchor list (persistent waves, per-XCD queues as in the
+// walk; one anchor per queue slot): a wave builds its anchor's lists, stores
+// them in the pool and their place in arec[anchor] (valid word 1; all zero when
+// they did not fit, and the anchor's groups walk from the root).
+__global__ __launch_bounds__(64) void k_walk_prefix(WalkArgs a, unsigned *__restrict__ prefix_head,
+                                                    const unsigned *__restrict__ acount,
+                                                    const uint32_t *__restrict__ alist,
+                                                    unsigned long long *__restrict__ pool_head,
+                                                    uint4 *__restrict__ arec, uint32_t *__restrict__ pool,
+                                                    unsigned long long pool_cap,
+                                                    uint32_t *__restrict__ pscr) {
+    __shared__ uint32_t s_stk[PREFIX_RING];
+    const unsigned ln = lane64();
+    uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
+    uint32_t *pf = pscr + (size_t)blockIdx.x * PREFIX_SCRATCH;
+    if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
+    const unsigned nanchor = uniform(*acount);
+    QueueCursor qc = queue_start();
+    for (;;) {
+        const unsigned slot = queue_next(prefix_head, nanchor, qc);
+        if (slot >= nanchor) break;
+        const unsigned A = uniform(alist[slot]);
+        unsigned nf, ns;
+        bool ok = anchor_lists(a, A, s_stk, gstk, pf, &nf, &ns);
+        nf = uniform(nf);
+        ns = uniform(ns);
+        unsigned long long off64 = 0;
+        if (ok) {  // every lane calls the atomic (lane 0 adds), see queue_next
+            off64 = atomicAdd(pool_head, ln == 0 ? (unsigned long long)(nf + ns) : 0ull);
+            off64 = ((unsigned long long)uniform((unsigned)(off64 >> 32)) << 32) | uniform((unsigned)off64);
+            ok = off64 + nf + ns <= pool_cap;
+        }
+        const unsigned off = (unsigned)off64;  // < 2^32 when ok
+        if (ok) {
+            for (unsigned i = ln; i < nf; i += 64) pool[off + i] = pf[i];
+            const uint32_t *pseed = pf + PREFIX_F_CAP + PREFIX_S_CAP;
+            for (unsigned i = ln; i < ns; i += 64) pool[off + nf + i] = pseed[i];
+        }
+        // every lane stores the same record: no lane-dependent branch in this loop
+        arec[A] = ok ? make_uint4(off, nf, ns, 1u) : make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, float G, int precision,
                        const uint32_t *order, const uint32_t *qlen, const uint8_t *active, float *acc, float *pot,
-                       hipStream_t s) {
+                       int anchor_up, hipStream_t s) {
     (void)n;
     WalkArgs a;
     a.hdr = b.hdr;
@@ -524,12 +791,30 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
     a.G = G;
     a.pc_cap = b.pc_cap;
     a.pp_cap = b.pp_cap;
-    if (precision == 2)
-        hipLaunchKernelGGL(k_walk<2>, dim3(b.walk_waves), dim3(64), 0, s, a);
-    else if (precision == 1)
-        hipLaunchKernelGGL(k_walk<1>, dim3(b.walk_waves), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_walk<0>, dim3(b.walk_waves), dim3(64), 0, s, a);
+    a.cbox = b.cbox;
+    a.anchor = b.anchor;
+    a.arec = b.arec;
+    a.pool = b.pool;
+    const bool shared = anchor_up > 0 && b.anchor;
+    if (shared) {
+        const unsigned grid = min((b.n_max + 255u) / 256u, 2048u);
+        hipLaunchKernelGGL(k_walk_anchor, dim3(grid), dim3(256), 0, s, b.hdr, b.groups, b.topo, anchor_up, b.anchor,
+                           b.arec);
+        hipLaunchKernelGGL(k_walk_claim, dim3(grid), dim3(256), 0, s, b.hdr, b.anchor, order, qlen, b.arec, b.alist,
+                           &b.hdr->anchor_count);
+        hipLaunchKernelGGL(k_walk_prefix, dim3(b.walk_waves), dim3(64), 0, s, a, b.hdr->prefix_head,
+                           &b.hdr->anchor_count, b.alist, &b.hdr->pool_head, b.arec, b.pool, b.pool_cap, b.pscr);
+    }
+    if (precision == 2) {
+        if (shared) hipLaunchKernelGGL((k_walk<2, true>), dim3(b.walk_waves), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_walk<2, false>), dim3(b.walk_waves), dim3(64), 0, s, a);
+    } else if (precision == 1) {
+        if (shared) hipLaunchKernelGGL((k_walk<1, true>), dim3(b.walk_waves), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_walk<1, false>), dim3(b.walk_waves), dim3(64), 0, s, a);
+    } else {
+        if (shared) hipLaunchKernelGGL((k_walk<0, true>), dim3(b.walk_waves), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_walk<0, false>), dim3(b.walk_waves), dim3(64), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ class MibhError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("ncrit", C.c_int32), ("group_cap", C.c_int32), ("eps2", C.c_float), ("G", C.c_float),
                 ("precision", C.c_int32), ("walk_waves", C.c_int32), ("pc_cap", C.c_int32),
-                ("pp_cap", C.c_int32), ("max_systems", C.c_int32)]
+                ("pp_cap", C.c_int32), ("max_systems", C.c_int32), ("anchor_up", C.c_int32)]
 
 
 class Stats(C.Structure):

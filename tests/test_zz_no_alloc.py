@@ -27,7 +27,7 @@ def _run_static(pos, mass, theta):
 
 def _run_context(pos, mass, theta):
     import torch
-    ctx = gpu_context(len(mass))
+    ctx = gpu_context(len(mass), anchor_up=0)  # the static workspace walks from the root
     acc, pot = ctx.forces(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda(), theta)
     ctx.sync()
     return acc.cpu().numpy(), pot.cpu().numpy()

@@ -381,19 +381,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     uint32_t *__restrict__ vout, const uint8_t *__restrict__ sys8, unsigned n, int shift,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ btot, unsigned ntiles) {
     constexpr int NW = SORT_THREADS / 64;
-    static_assert(SORT_THREADS == RADIX, "one thread per digit");
+    static_assert(SORT_THREADS % RADIX == 0, "the first RADIX threads look after one digit each");
     __shared__ uint32_t wcnt[NW][RADIX];
     __shared__ uint32_t gshift[RADIX];  // output position of tile position i of digit d: gshift[d] + i
     __shared__ unsigned s_wave[NW + 1];
     __shared__ uint64_t s_key[SORT_TILE];
     __shared__ uint32_t s_val[SORT_TILE];
     const unsigned w = threadIdx.x >> 6, ln = lane64();
-    const unsigned dt = threadIdx.x;  // the digit this thread looks after
+    const bool owner = threadIdx.x < (unsigned)RADIX;
+    const unsigned dt = owner ? threadIdx.x : 0u;  // the digit this thread looks after
     unsigned total;
     // start of digit dt's run of this tile in the output
-    const unsigned gstart = block_excl_scan<SORT_THREADS>(btot[dt], s_wave, &total) +
-                            hist[(size_t)dt * ntiles + blockIdx.x];
-    for (int v = 0; v < NW; v++) wcnt[v][dt] = 0;
+    const unsigned gstart = block_excl_scan<SORT_THREADS>(owner ? btot[dt] : 0u, s_wave, &total) +
+                            (owner ? hist[(size_t)dt * ntiles + blockIdx.x] : 0u);
+    if (owner)
+        for (int v = 0; v < NW; v++) wcnt[v][dt] = 0;
     __syncthreads();
     const unsigned base = blockIdx.x * SORT_TILE + w * (64 * SORT_ITEMS);
     uint64_t key[SORT_ITEMS];
@@ -415,14 +417,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         // tile position of the first element of digit dt from wave v: digits
         // before dt, then waves before v
         unsigned run = 0;
-        for (int v = 0; v < NW; v++) {
-            const unsigned c = wcnt[v][dt];
-            wcnt[v][dt] = run;
-            run += c;
-        }
+        if (owner)
+            for (int v = 0; v < NW; v++) {
+                const unsigned c = wcnt[v][dt];
+                wcnt[v][dt] = run;
+                run += c;
+            }
         const unsigned lstart = block_excl_scan<SORT_THREADS>(run, s_wave, &total);
-        for (int v = 0; v < NW; v++) wcnt[v][dt] += lstart;
-        gshift[dt] = gstart - lstart;  // modulo 2^32; gshift + i >= 0 for the tile positions of dt
+        if (owner) {
+            for (int v = 0; v < NW; v++) wcnt[v][dt] += lstart;
+            gshift[dt] = gstart - lstart;  // modulo 2^32; gshift + i >= 0 for the tile positions of dt
+        }
     }
     __syncthreads();
 #pragma unroll

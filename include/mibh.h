@@ -225,6 +225,9 @@ typedef struct {
     uint64_t sum_pc;       /* sum over particles of their group's particle-cell count */
     uint64_t sum_pp;       /* sum over particles of their group's particle-particle count */
     uint32_t flags;        /* device flags: 1 non-finite, 2 negative mass, 4 stack, 8 cell capacity */
+    uint32_t anchors;      /* shared-prefix walk (anchor_up > 0): anchor cells of the last walk */
+    uint32_t anchor_fallbacks; /* of those, anchors whose lists did not fit their room (their
+                                  groups walked from the root: same results, slower) */
 } mibh_stats_t;
 mibh_status mibh_stats(mibh_ctx *ctx, mibh_stats_t *out);
 

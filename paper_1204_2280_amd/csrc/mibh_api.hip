@@ -690,6 +690,10 @@ mibh_status mibh_stats(mibh_ctx *ctx, mibh_stats_t *out) {
     out->root_k = c0.k;
     out->nsys = ctx->nsys;
     out->flags = h.flags;
+    if (ctx->p.anchor_up > 0) {
+        out->anchors = h.anchor_count;
+        out->anchor_fallbacks = h.anchor_fail;
+    }
     int depth = 0;
     for (int l = 0; l <= KEY_LEVELS; l++)
         if (h.lvl_begin[l + 1] > h.lvl_begin[l]) depth = l;

@@ -74,7 +74,8 @@ struct Header {
     alignas(256) unsigned prefix_head[8 * 64];
     alignas(256) unsigned long long pool_head;
     unsigned anchor_count;
-    unsigned pool_pad[61];
+    unsigned anchor_fail;  // anchors whose lists did not fit
+    unsigned pool_pad[60];
 };
 
 // Group queues of the persistent walks.  gfx950 deals the workgroups of a

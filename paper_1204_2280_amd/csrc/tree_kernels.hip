@@ -1084,6 +1084,7 @@ __global__ __launch_bounds__(256) void k_mac_prep(Header *__restrict__ hdr, cons
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr->pool_head = 0;
         hdr->anchor_count = 0;
+        hdr->anchor_fail = 0;
     }
     for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < nc; c += gridDim.x * 256u) {
         const double ro = lside[c] / theta + delta[c];

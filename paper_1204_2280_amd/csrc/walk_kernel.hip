@@ -732,7 +732,7 @@ __global__ __launch_bounds__(64) void k_walk_prefix(WalkArgs a, unsigned *__rest
                                                     unsigned long long *__restrict__ pool_head,
                                                     uint4 *__restrict__ arec, uint32_t *__restrict__ pool,
                                                     unsigned long long pool_cap,
-                                                    uint32_t *__restrict__ pscr) {
+                                                    uint32_t *__restrict__ pscr, unsigned *__restrict__ nfail) {
     __shared__ uint32_t s_stk[PREFIX_RING];
     const unsigned ln = lane64();
     uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
@@ -754,6 +754,7 @@ __global__ __launch_bounds__(64) void k_walk_prefix(WalkArgs a, unsigned *__rest
             off64 = ((unsigned long long)uniform((unsigned)(off64 >> 32)) << 32) | uniform((unsigned)off64);
             ok = off64 + nf + ns <= pool_cap;
         }
+        if (!ok) atomicAdd(nfail, ln == 0 ? 1u : 0u);  // ok is wave-uniform
         const unsigned off = (unsigned)off64;  // < 2^32 when ok
         if (ok) {
             for (unsigned i = ln; i < nf; i += 64) pool[off + i] = pf[i];
@@ -803,7 +804,8 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
         hipLaunchKernelGGL(k_walk_claim, dim3(grid), dim3(256), 0, s, b.hdr, b.anchor, order, qlen, b.arec, b.alist,
                            &b.hdr->anchor_count);
         hipLaunchKernelGGL(k_walk_prefix, dim3(b.walk_waves), dim3(64), 0, s, a, b.hdr->prefix_head,
-                           &b.hdr->anchor_count, b.alist, &b.hdr->pool_head, b.arec, b.pool, b.pool_cap, b.pscr);
+                           &b.hdr->anchor_count, b.alist, &b.hdr->pool_head, b.arec, b.pool, b.pool_cap, b.pscr,
+                           &b.hdr->anchor_fail);
     }
     if (precision == 2) {
         if (shared) hipLaunchKernelGGL((k_walk<2, true>), dim3(b.walk_waves), dim3(64), 0, s, a);

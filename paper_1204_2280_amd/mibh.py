@@ -55,7 +55,8 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("ncells", C.c_int64), ("ngroups", C.c_int64), ("nleaves", C.c_int64),
                 ("depth", C.c_int32), ("root_k", C.c_int32), ("nsys", C.c_int32), ("sum_pc", C.c_uint64),
-                ("sum_pp", C.c_uint64), ("flags", C.c_uint32)]
+                ("sum_pp", C.c_uint64), ("flags", C.c_uint32), ("anchors", C.c_uint32),
+                ("anchor_fallbacks", C.c_uint32)]
 
 
 _lib = None

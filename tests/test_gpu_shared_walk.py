@@ -94,7 +94,9 @@ def test_shared_walk_full_size_counts_equal_plain_walk():
         acc, pot = ctx.forces(p, m, 0.75)
         st = ctx.stats()
         out[up] = (ctx.export("counts").cpu().numpy().view(np.uint32), acc.cpu().numpy().astype(np.float64),
-                   st.get("flags", 0))
+                   st["flags"])
+        print(f"[gpu] 2^22 up={up}: {st['anchors']} anchors, {st['anchor_fallbacks']} without room", flush=True)
+        assert (st["anchors"] > 0) == (up > 0)
         del ctx
     for up in (2, 3):
         np.testing.assert_array_equal(out[0][0], out[up][0])

@@ -793,7 +793,7 @@ def main():
         "tree": {"ncells": st["ncells"], "ngroups": st["ngroups"], "nleaves": st["nleaves"],
                  "depth": st["depth"]},
         "roofline": {
-            "kernel": "k_walk (group tree walk)",
+            "kernel": "walk stage: k_walk_anchor + k_walk_claim + k_walk_prefix (shared anchor lists) + k_walk (group tree walk)",
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,

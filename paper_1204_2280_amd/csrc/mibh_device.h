@@ -120,7 +120,8 @@ constexpr unsigned WALK_LSTACK = 512;   // cell stack in LDS (spills to the glob
 // Shared-prefix walk: per-wave scratch for an anchor cell's lists: the cells it
 // accepts (F), then the cells left for each group, raw and sorted by level (S).
 constexpr unsigned PREFIX_F_CAP = 3072;
-constexpr unsigned PREFIX_S_CAP = 512;  // a seed of <= 512 cells keeps the stack within STACK_CAP
+constexpr unsigned PREFIX_S_CAP = 512;  // a seed of <= 512 cells fits the walk's LDS ring and keeps
+                                        // the stack within STACK_CAP
 constexpr unsigned PREFIX_SCRATCH = PREFIX_F_CAP + 2 * PREFIX_S_CAP;
 // Pool words per particle for all anchors' lists: 16 >> (anchor_up - 1), as
 // anchors get fewer and larger with their height (at N = 2^22 in a Plummer

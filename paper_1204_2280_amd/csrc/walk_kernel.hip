@@ -329,6 +329,7 @@ template <int PREC, bool SHARED>
 __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
     constexpr unsigned MASK = WALK_LSTACK - 1;
     static_assert((WALK_LSTACK & MASK) == 0 && WALK_LSTACK >= 512, "stack ring must hold one step's pushes");
+    static_assert(PREFIX_S_CAP <= WALK_LSTACK, "an anchor's cells left fit the empty ring");
     __shared__ uint32_t s_stk[WALK_LSTACK];
     // the compensated walks' compensations take 768 more bytes of LDS: their
     // particle-cell list is shorter by as much, so 16 waves still fit a CU
@@ -401,13 +402,14 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             // the lists shared by the groups below this group's anchor cell: its
             // accepted cells go into the particle-cell list as they are, and the
             // stack starts with the cells left (sorted by level, shallowest at the
-            // bottom, so that stack levels never decrease towards the top)
+            // bottom, so that stack levels never decrease towards the top), in the
+            // LDS ring, which is empty here and holds all of them (<= PREFIX_S_CAP)
             const uint4 rec = a.arec[uniform(a.anchor[g])];
             seeded = uniform(rec.w) == 1u;
             if (seeded) {
                 const unsigned off = uniform(rec.x), nf = uniform(rec.y), ns = uniform(rec.z);
-                for (unsigned i = ln; i < ns; i += 64) gstk[i] = a.pool[off + nf + i];
-                gtop = ns;
+                for (unsigned i = ln; i < ns; i += 64) s_stk[i] = a.pool[off + nf + i];
+                st = ns;
                 for (unsigned k0 = 0; k0 < nf; k0 += 64) {
                     const unsigned cnt = min(64u, nf - k0);
                     if (npc + cnt > pc_cap)

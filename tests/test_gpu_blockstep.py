@@ -37,14 +37,15 @@ def test_one_level_rebuilding_every_tick_is_the_leapfrog():
     assert bool((P == P2).all()) and bool((V == V2).all())
 
 
-def test_block_steps_match_oracle(orc):
+@pytest.mark.parametrize("tol", [0.05, -1.0])  # refits with a work-growth trigger; a rebuild before every walk
+def test_block_steps_match_oracle(orc, tol):
     from oracle import blockstep
     n, theta, eps2 = 1 << 12, 0.75, 1e-4
-    dt_max, R, eta, eps, nbig, tol = 1 / 16, 4, 0.1, 0.1, 2, 0.05
+    dt_max, R, eta, eps, nbig = 1 / 16, 4, 0.1, 0.1, 2
     pos, vel, mass = W.plummer(n, 13)
     ctx = gpu_context(n, eps2=eps2)
     P, V, M = _t(pos), _t(vel), _t(mass)
-    print(f"[gpu] block steps n={n} R={R} nbig={nbig}", flush=True)
+    print(f"[gpu] block steps n={n} R={R} nbig={nbig} rebuild tolerance {tol}", flush=True)
     acc, pot, lev, st, log = ctx.block_run(P, V, M, theta, dt_max, R, eta, eps, nbig, rebuild_tol=tol)
     ctx.sync()
     x, v, a, p, olev, ost, olog = blockstep.block_run(pos, vel, mass, theta, dt_max, R, eta, eps, nbig, tol=tol,

@@ -326,6 +326,11 @@ __device__ __forceinline__ unsigned radix_digit(uint64_t key, uint32_t val, int 
     return shift >= 0 ? (unsigned)(key >> shift) & (RADIX - 1) : (unsigned)sys8[val];
 }
 
+// AGG: equal digits of a wave are matched first (8 ballots) and their leader
+// adds their number, one LDS atomic per distinct digit instead of per element:
+// cheaper where digits are concentrated (the high digits of clustered keys,
+// the system digit), where per-element atomics collide on one counter.
+template <bool AGG>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__restrict__ keys,
                                                              const uint32_t *__restrict__ vals,
                                                              const uint8_t *__restrict__ sys8,
@@ -344,7 +349,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__r
         const unsigned d = valid ? radix_digit(shift >= 0 ? keys[idx] : 0ull, shift >= 0 ? 0u : vals[idx], shift,
                                                sys8)
                                  : 0u;
-        if (valid) atomicAdd(&h[w][d], 1u);  // integer counts: the order of the adds does not matter
+        if (AGG) {
+            const unsigned long long peers = match_digit(d, __ballot(valid));
+            if (valid && ln == (unsigned)(__ffsll((long long)peers) - 1)) atomicAdd(&h[w][d], (unsigned)__popcll(peers));
+        } else if (valid) {
+            atomicAdd(&h[w][d], 1u);  // integer counts: the order of the adds does not matter
+        }
     }
     __syncthreads();
     for (unsigned d = threadIdx.x; d < RADIX; d += SORT_THREADS) {
@@ -451,6 +461,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
 }
 
+#ifndef MIBH_HIST_AGG_SHIFT
+#define MIBH_HIST_AGG_SHIFT 48  // passes over key bits 48.. (and the system pass) match digits first
+                                // (sorting at 2^22: 404 us without, 401 us with, 439 us for every pass)
+#endif
+
 // 8 passes over the 60-bit keys; a batch adds a last pass by system, which
 // gathers each system's particles (in key order) into its input range.
 hipError_t launch_sort(const Buffers &b, unsigned n, unsigned nsys, hipStream_t s) {
@@ -459,8 +474,12 @@ hipError_t launch_sort(const Buffers &b, unsigned n, unsigned nsys, hipStream_t 
     for (int pass = 0; pass < passes; pass++) {
         const int src = pass & 1, dst = src ^ 1;
         const int shift = pass < SORT_PASSES ? pass * RADIX_BITS : -1;
-        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src], b.vals[src],
-                           b.sys8, n, shift, b.hist, ntiles);
+        if (shift < 0 || shift >= MIBH_HIST_AGG_SHIFT)
+            hipLaunchKernelGGL(k_radix_hist<true>, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src], b.vals[src],
+                               b.sys8, n, shift, b.hist, ntiles);
+        else
+            hipLaunchKernelGGL(k_radix_hist<false>, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src], b.vals[src],
+                               b.sys8, n, shift, b.hist, ntiles);
         hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(256), 0, s, b.hist, ntiles, b.btot);
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(SORT_THREADS), 0, s, b.keys[src],
                            pass == 0 ? (const uint32_t *)nullptr : b.vals[src], b.keys[dst], b.vals[dst],

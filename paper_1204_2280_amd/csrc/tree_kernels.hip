@@ -395,8 +395,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     __shared__ uint32_t wcnt[NW][RADIX];
     __shared__ uint32_t gshift[RADIX];  // output position of tile position i of digit d: gshift[d] + i
     __shared__ unsigned s_wave[NW + 1];
-    __shared__ uint64_t s_key[SORT_TILE];
-    __shared__ uint32_t s_val[SORT_TILE];
+    __shared__ uint64_t s_key[SORT_TILE];  // the indices (as 32-bit words), then the keys
     const unsigned w = threadIdx.x >> 6, ln = lane64();
     const bool owner = threadIdx.x < (unsigned)RADIX;
     const unsigned dt = owner ? threadIdx.x : 0u;  // the digit this thread looks after
@@ -440,24 +439,46 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         }
     }
     __syncthreads();
+    // the indices, then the keys, through the same LDS (a third less LDS, three
+    // blocks per CU instead of two: sorting 402 -> 395 us at N = 2^22); each
+    // thread keeps the indices of its tile positions between the two phases,
+    // since the system pass needs an element's index for its digit
+    unsigned lpos[SORT_ITEMS];
+    uint32_t *s_val = reinterpret_cast<uint32_t *>(s_key);
 #pragma unroll
     for (int t = 0; t < SORT_ITEMS; t++) {
         const unsigned idx = base + t * 64 + ln;
-        if (idx < n) {
-            const unsigned d = radix_digit(key[t], val[t], shift, sys8);
-            const unsigned lp = wcnt[w][d] + rank[t];
-            s_key[lp] = key[t];
-            s_val[lp] = val[t];
-        }
+        const unsigned d = idx < n ? radix_digit(key[t], val[t], shift, sys8) : 0u;
+        lpos[t] = wcnt[w][d] + rank[t];
+    }
+    const unsigned cnt = min((unsigned)SORT_TILE, n - blockIdx.x * SORT_TILE);
+    uint32_t vpos[SORT_ITEMS];  // the index at tile position threadIdx.x + t * SORT_THREADS
+    // phase 1: the indices
+#pragma unroll
+    for (int t = 0; t < SORT_ITEMS; t++)
+        if (base + t * 64 + ln < n) s_val[lpos[t]] = val[t];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < SORT_ITEMS; t++) {
+        const unsigned i = threadIdx.x + t * SORT_THREADS;
+        vpos[t] = i < cnt ? s_val[i] : 0u;
     }
     __syncthreads();
-    const unsigned cnt = min((unsigned)SORT_TILE, n - blockIdx.x * SORT_TILE);
-    for (unsigned i = threadIdx.x; i < cnt; i += SORT_THREADS) {
-        const uint64_t k = s_key[i];
-        const uint32_t v = s_val[i];
-        const unsigned p = gshift[radix_digit(k, v, shift, sys8)] + i;
-        kout[p] = k;
-        vout[p] = v;
+    // phase 2: the keys; position i's output slot from its digit
+#pragma unroll
+    for (int t = 0; t < SORT_ITEMS; t++)
+        if (base + t * 64 + ln < n) s_key[lpos[t]] = key[t];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < SORT_ITEMS; t++) {
+        const unsigned i = threadIdx.x + t * SORT_THREADS;
+        if (i < cnt) {
+            const uint64_t k = s_key[i];
+            const uint32_t v = vpos[t];
+            const unsigned p = gshift[radix_digit(k, v, shift, sys8)] + i;
+            kout[p] = k;
+            vout[p] = v;
+        }
     }
 }
 

@@ -557,7 +557,8 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
 //   * a cell A's box accepts (the group MAC with A's box) is accepted by every
 //     group inside A: the group's box lies inside A's, so its rounded distance
 //     is no smaller; such a cell is never an ancestor of a group (it would
-//     contain A or lie inside it);
+//     either contain A, and ancestors of A are opened, or lie inside A, with
+//     its centre of mass inside A's box at distance 0);
 //   * any other cell is left to each group.
 // Each group then starts with the accepted cells (F) in its particle-cell list
 // and the cells left (S) on its stack and walks on as usual: the same cells

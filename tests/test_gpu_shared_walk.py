@@ -104,3 +104,23 @@ def test_shared_walk_full_size_counts_equal_plain_walk():
         e = rel_err(out[up][1], out[0][1])
         print(f"[gpu] shared walk at 2^22, up={up}: counts equal, acc p99 difference {p99(e):.2e}", flush=True)
         assert p99(e) <= 1e-6
+
+
+@pytest.mark.parametrize("theta", [0.1, 1e-4])
+def test_anchors_without_room_fall_back_to_the_root_walk(orc, theta):
+    """At small opening angles an anchor's cells left (or accepted) outgrow the
+    room of its lists; its groups then walk from the root, and the counts stay
+    equal to the oracle's."""
+    pos, _, mass = W.plummer(20000, 9, with_velocities=False)
+    T = orc.Tree(pos, mass)
+    T.walk(theta)
+    npc, npp = T.counts()
+    acc, _ = T.forces()
+    ctx = gpu_context(len(mass), anchor_up=3)
+    g = run_gpu(ctx, pos, mass, theta, exports=("counts",))
+    st = ctx.stats()
+    print(f"[gpu] theta={theta}: {st['anchors']} anchors, {st['anchor_fallbacks']} without room", flush=True)
+    assert st["anchor_fallbacks"] > 0
+    np.testing.assert_array_equal(g["counts"][:, 0], npc)
+    np.testing.assert_array_equal(g["counts"][:, 1], npp)
+    assert p99(rel_err(g["acc"], acc)) <= TOL_P99

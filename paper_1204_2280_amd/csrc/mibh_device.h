@@ -30,7 +30,7 @@ constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
 #define MIBH_BUILD_THREADS 512
 #endif
 constexpr int BUILD_THREADS = MIBH_BUILD_THREADS;
-constexpr int MAX_WINDOW = 64;          // largest group_cap (halo of the build window)
+constexpr int MAX_WINDOW = 64;          // largest ncrit and group_cap (a build wave's window reach)
 constexpr int BBOX_BLOCKS = 1024;
 constexpr int ENERGY_BLOCKS = 1024;
 constexpr int ENERGY_THREADS = 256;

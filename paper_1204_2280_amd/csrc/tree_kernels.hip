@@ -548,78 +548,96 @@ hipError_t launch_reorder(const Buffers &b, unsigned n, unsigned nsys, hipStream
 // breadth-first order (level, then key).
 // --------------------------------------------------------------------------
 
+// Value at position `pos` (0..127, or 0..191 with three registers) of an array
+// held as consecutive 64-lane registers r0, r1, r2: lane pos & 63 of register
+// pos >> 6.  Every lane passes its own position; the lane index is shared by the
+// shuffles, the register is picked afterwards.
+__device__ __forceinline__ int wave_at3(int r0, int r1, int r2, unsigned pos) {
+    const int lane = (int)(pos & 63u);
+    const int v0 = __shfl(r0, lane, 64), v1 = __shfl(r1, lane, 64), v2 = __shfl(r2, lane, 64);
+    return pos < 64u ? v0 : pos < 128u ? v1 : v2;
+}
+__device__ __forceinline__ int wave_at2(int r0, int r1, unsigned pos) {
+    const int lane = (int)(pos & 63u);
+    const int v0 = __shfl(r0, lane, 64), v1 = __shfl(r1, lane, 64);
+    return pos < 64u ? v0 : v1;
+}
+
 __global__ __launch_bounds__(BUILD_THREADS) void k_build_count(
     const int8_t *__restrict__ cl, const uint64_t *__restrict__ keys, unsigned n, unsigned nsys,
     const uint32_t *__restrict__ sys_off, int ncrit, int gcap, uchar4 *__restrict__ lvinfo,
     uint32_t *__restrict__ blkcnt, unsigned nblk) {
-    constexpr int H = MAX_WINDOW;
     constexpr int NW = BUILD_THREADS / 64;
-    constexpr int A = BUILD_THREADS + 2 * H + 1;   // cl of particles base - H .. base + BUILD_THREADS + H
-    constexpr int B = BUILD_THREADS + H;           // window starts
-    __shared__ int8_t s_cl[A];
-    __shared__ int8_t s_t[3][A];                   // doubling tables of minima (two in turn, one kept)
-    __shared__ int8_t s_wn[B];
-    __shared__ int8_t s_wg[B];
-    __shared__ int8_t s_m[4][B];                   // doubling tables of maxima (two per window size)
     __shared__ uint32_t s_cnt[NW][NCOUNTERS];
     const unsigned base = blockIdx.x * BUILD_THREADS;
-    for (int j = threadIdx.x; j < A; j += BUILD_THREADS) {
-        const long long gi = (long long)base - H + j;
-        s_cl[j] = (gi >= 0 && gi < (long long)n) ? cl[gi] : (int8_t)-1;
-    }
-    __syncthreads();
-    // Sliding-window extrema by doubling: after step k a table holds the
-    // minimum (maximum) of 2^k consecutive entries starting at each index, and
-    // a window of length w is covered by two such runs of length 2^floor(log2 w).
-    // s_wn[a] = min cl[a+1 .. a+ncrit], s_wg[a] = min cl[a+1 .. a+gcap]: the
-    // inner boundaries of the windows that start at a.
-    const int kn = 31 - __clz(ncrit), kg = 31 - __clz(gcap);
-    {
-        const int8_t *cur = s_cl, *tn = s_cl;
-        for (int k = 0; k < kg; k++) {
-            int8_t *nxt = s_t[k & 1];
-            const int sh = 1 << k;
-            for (int j = threadIdx.x; j < A; j += BUILD_THREADS) {
-                const int8_t v = j + sh < A ? (int8_t)min((int)cur[j], (int)cur[j + sh]) : cur[j];
-                nxt[j] = v;
-                if (k + 1 == kn) s_t[2][j] = v;
-            }
-            __syncthreads();
-            cur = nxt;
-            if (k + 1 == kn) tn = s_t[2];
-        }
-        for (int a = threadIdx.x; a < B; a += BUILD_THREADS) {
-            s_wn[a] = (int8_t)min((int)tn[a + 1], (int)tn[a + 1 + ncrit - (1 << kn)]);
-            s_wg[a] = (int8_t)min((int)cur[a + 1], (int)cur[a + 1 + gcap - (1 << kg)]);
-        }
-        __syncthreads();
-    }
-    // ln = max s_wn[tl - ncrit .. tl], lg = max s_wg[tl - gcap .. tl]: the
-    // windows of ncrit + 1 (gcap + 1) particles that contain particle tl.
     const unsigned i = base + threadIdx.x;
     const bool valid = i < n;
-    const int tl = threadIdx.x + H;
+    // Each wave on its own, in registers: the cl values of positions wb - 64 ..
+    // wb + 127 (wb = the wave's first particle; -1 outside the particles) cover
+    // every window that contains one of the wave's particles (ncrit, gcap <= 64).
+    // This replaced doubling tables in LDS with 13 block barriers (tree
+    // construction at N = 2^22: 148 -> 139 us).
+    static_assert(MAX_WINDOW <= 64, "windows reach at most one wave width either side");
+    const unsigned ln_ = lane64();
+    const long long wb = (long long)base + (long long)(threadIdx.x & ~63u);
+    int t[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        const long long j = wb - 64 + 64 * r + ln_;
+        t[r] = (j >= 0 && j < (long long)n) ? (int)cl[j] : -1;
+    }
+    const int ci = t[1];
+    // Minima by doubling: after step k, t[r] at lane l is the minimum of the 2^k
+    // values from position 64 r + l on (positions past 191 are never asked for).
+    const int kn = 31 - __clz(ncrit), kg = 31 - __clz(gcap), kmax = max(kn, kg);
+    int tn[3] = {t[0], t[1], t[2]}, tg[3] = {t[0], t[1], t[2]};
+    for (int k = 0; k < kmax; k++) {
+        const unsigned sh = 1u << k;
+        const int src = (int)((ln_ + sh) & 63u);
+        const bool wrap = ln_ + sh >= 64u;
+        const int a0 = __shfl(t[0], src, 64), a1 = __shfl(t[1], src, 64), a2 = __shfl(t[2], src, 64);
+        t[0] = min(t[0], wrap ? a1 : a0);
+        t[1] = min(t[1], wrap ? a2 : a1);
+        t[2] = min(t[2], wrap ? t[2] : a2);
+        if (k + 1 == kn) { tn[0] = t[0]; tn[1] = t[1]; tn[2] = t[2]; }
+        if (k + 1 == kg) { tg[0] = t[0]; tg[1] = t[1]; tg[2] = t[2]; }
+    }
+    // Window minima for the window starts a = wb - 64 + 64 r + lane (r = 0, 1):
+    // min cl[a+1 .. a+w] = min(T[a+1], T[a+1+w-2^k]); a start's position is its
+    // array position, so a+1 sits at 64 r + lane + 1.
+    int mn[2], mg[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        const unsigned p = 64u * r + ln_ + 1u;
+        mn[r] = min(wave_at3(tn[0], tn[1], tn[2], p), wave_at3(tn[0], tn[1], tn[2], p + (unsigned)(ncrit - (1 << kn))));
+        mg[r] = min(wave_at3(tg[0], tg[1], tg[2], p), wave_at3(tg[0], tg[1], tg[2], p + (unsigned)(gcap - (1 << kg))));
+    }
+    // ln = max of the window minima over the starts tl - w .. tl (tl = the
+    // particle's start position, 64 + lane), maxima by doubling over the 128 starts.
     int ln, lg;
     {
-        const int kn2 = 31 - __clz(ncrit + 1), kg2 = 31 - __clz(gcap + 1);
-        const int8_t *cn = s_wn, *cg = s_wg;
-        for (int k = 0; k < kg2; k++) {
-            int8_t *nn = s_m[k & 1], *ng = s_m[2 + (k & 1)];
-            const int sh = 1 << k;
-            for (int j = threadIdx.x; j < B; j += BUILD_THREADS) {
-                if (k < kn2) nn[j] = j + sh < B ? (int8_t)max((int)cn[j], (int)cn[j + sh]) : cn[j];
-                ng[j] = j + sh < B ? (int8_t)max((int)cg[j], (int)cg[j + sh]) : cg[j];
-            }
-            __syncthreads();
-            if (k < kn2) cn = nn;
-            cg = ng;
+        const int kn2 = 31 - __clz(ncrit + 1), kg2 = 31 - __clz(gcap + 1), kmax2 = max(kn2, kg2);
+        int un[2] = {mn[0], mn[1]}, ug[2] = {mg[0], mg[1]};
+        int vn[2] = {mn[0], mn[1]}, vg[2] = {mg[0], mg[1]};  // the tables at kn2 and kg2
+        for (int k = 0; k < kmax2; k++) {
+            const unsigned sh = 1u << k;
+            const int src = (int)((ln_ + sh) & 63u);
+            const bool wrap = ln_ + sh >= 64u;
+            const int b0 = __shfl(un[0], src, 64), b1 = __shfl(un[1], src, 64);
+            const int c0 = __shfl(ug[0], src, 64), c1 = __shfl(ug[1], src, 64);
+            un[0] = max(un[0], wrap ? b1 : b0);
+            un[1] = max(un[1], wrap ? un[1] : b1);
+            ug[0] = max(ug[0], wrap ? c1 : c0);
+            ug[1] = max(ug[1], wrap ? ug[1] : c1);
+            if (k + 1 == kn2) { vn[0] = un[0]; vn[1] = un[1]; }
+            if (k + 1 == kg2) { vg[0] = ug[0]; vg[1] = ug[1]; }
         }
-        ln = max((int)cn[tl - ncrit], (int)cn[tl - (1 << kn2) + 1]);
-        lg = max((int)cg[tl - gcap], (int)cg[tl - (1 << kg2) + 1]);
+        const unsigned tl = 64u + ln_;
+        ln = max(wave_at2(vn[0], vn[1], tl - (unsigned)ncrit), wave_at2(vn[0], vn[1], tl - (1u << kn2) + 1u));
+        lg = max(wave_at2(vg[0], vg[1], tl - (unsigned)gcap), wave_at2(vg[0], vg[1], tl - (1u << kg2) + 1u));
     }
     const int leaf = ln < 0 ? 0 : min(ln + 1, KEY_LEVELS);
     const int glev = lg < 0 ? 0 : min(lg + 1, KEY_LEVELS);
-    const int ci = s_cl[tl];
     const int clo = ci + 1;
     bool gstart;
     unsigned oversized = 0;

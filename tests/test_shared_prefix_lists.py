@@ -127,3 +127,25 @@ def test_anchor_lists_give_the_oracle_lists(orc, workload):
             assert sorted(pc_r) == sorted(pc_o.tolist()) and sorted(pp_r) == sorted(pp_o.tolist())
             shared_total += len(F)
     assert shared_total > 0  # the anchors do decide cells for their groups
+
+
+def test_rounded_distances_are_monotone_in_the_box():
+    """The two facts the anchor lists rest on, in float32 with the kernels'
+    operation order: for a box B' inside a box B and any point m, the rounded
+    nearest-point squared distance of B' lies between B's nearest-point and
+    B's farthest-point squared distances (so B's acceptance implies B''s, and
+    a cell B surely opens is opened by B')."""
+    rng = np.random.default_rng(11)
+    for _ in range(20000):
+        scale = F32(10.0) ** F32(rng.integers(-3, 4))
+        lo = (rng.standard_normal(3) * scale).astype(F32)
+        hi = (lo + np.abs(rng.standard_normal(3)) * scale).astype(F32)
+        u, v = np.sort(rng.random((2, 3)), axis=0).astype(F32)
+        slo = np.clip((lo + (hi - lo) * u).astype(F32), lo, hi)
+        shi = np.clip((lo + (hi - lo) * v).astype(F32), slo, hi)
+        m = (rng.standard_normal(3) * scale * F32(3)).astype(F32)
+        if rng.random() < 0.5:  # points on box faces and inside, where the clamps matter
+            m = np.where(rng.random(3) < 0.5, lo, m).astype(F32)
+        near_b, far_b = _near_d2(lo, hi, m), _far_d2(lo, hi, m)
+        near_s = _near_d2(slo, shi, m)
+        assert near_b <= near_s <= far_b

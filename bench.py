@@ -791,7 +791,7 @@ def main():
         "walk_share": walk_ms / ms_step,
         "hbm_stages": hbm_stages(stage_ms, n, st["ncells"]),
         "tree": {"ncells": st["ncells"], "ngroups": st["ngroups"], "nleaves": st["nleaves"],
-                 "depth": st["depth"]},
+                 "depth": st["depth"], "anchors": st["anchors"], "anchors_without_room": st["anchor_fallbacks"]},
         "roofline": {
             "kernel": "walk stage: k_walk_anchor + k_walk_claim + k_walk_prefix (shared anchor lists) + k_walk (group tree walk)",
             "bound": "alu",

@@ -66,6 +66,22 @@ __device__ __forceinline__ unsigned small_excl_scan(unsigned v, unsigned *total)
     return r;
 }
 
+// Inclusive prefix sum over the wave, in lane order, of unsigned per-lane
+// values whose sums do not overflow: Hillis-Steele steps inside each row of 16
+// lanes (DPP row shifts 1, 2, 4, 8; a lane with no source lane adds 0), then the
+// row totals carried across rows by the GFX9 row broadcasts (lane 15 into rows 1
+// and 3, lane 31 into rows 2 and 3).  Six VALU instructions; the whole wave
+// must be active.
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // Sums each of the NV per-lane values v[0..NV) (NV = 64 or 32) over the wave.
 // With NV = 64 lane l gets the total of v[bitrev6(l)]; with NV = 32 lanes l and
 // l ^ 1 both get the total of v[bitrev6(l) & 31].  Stage with offset o pairs
@@ -107,13 +123,14 @@ __device__ __forceinline__ float transpose_reduce(float (&v)[NV]) {
 
 // The opening test, float32 with every operation rounded (no contraction):
 // d_a = max(max(bmin_a - c_a, c_a - bmax_a), 0), d2 = (dx dx + dy dy) + dz dz,
-// accept iff d2 > r_open^2.
+// accept iff d2 > r_open^2.  The inputs are finite (the walk refuses others),
+// so fmaxf (one v_max_f32) gives the maxima; where it may pick -0 instead of
+// +0 the square is +0 all the same.
 __device__ __forceinline__ bool mac_accept(float3 bmin, float3 bmax, float4 m) {
 #pragma clang fp contract(off)
-    float u, v, t;
-    u = bmin.x - m.x; v = m.x - bmax.x; t = u > v ? u : v; const float dx = t > 0.0f ? t : 0.0f;
-    u = bmin.y - m.y; v = m.y - bmax.y; t = u > v ? u : v; const float dy = t > 0.0f ? t : 0.0f;
-    u = bmin.z - m.z; v = m.z - bmax.z; t = u > v ? u : v; const float dz = t > 0.0f ? t : 0.0f;
+    const float dx = fmaxf(fmaxf(bmin.x - m.x, m.x - bmax.x), 0.0f);
+    const float dy = fmaxf(fmaxf(bmin.y - m.y, m.y - bmax.y), 0.0f);
+    const float dz = fmaxf(fmaxf(bmin.z - m.z, m.z - bmax.z), 0.0f);
     const float d2 = (dx * dx + dy * dy) + dz * dz;
     return d2 > m.w;
 }
@@ -125,10 +142,9 @@ __device__ __forceinline__ bool mac_accept(float3 bmin, float3 bmax, float4 m) {
 // far_d2 <= r_open^2 is opened for every group inside the box.
 __device__ __forceinline__ float far_d2(float3 bmin, float3 bmax, float4 m) {
 #pragma clang fp contract(off)
-    float u, v, t;
-    u = bmax.x - m.x; v = m.x - bmin.x; t = u > v ? u : v; const float dx = t > 0.0f ? t : 0.0f;
-    u = bmax.y - m.y; v = m.y - bmin.y; t = u > v ? u : v; const float dy = t > 0.0f ? t : 0.0f;
-    u = bmax.z - m.z; v = m.z - bmin.z; t = u > v ? u : v; const float dz = t > 0.0f ? t : 0.0f;
+    const float dx = fmaxf(fmaxf(bmax.x - m.x, m.x - bmin.x), 0.0f);
+    const float dy = fmaxf(fmaxf(bmax.y - m.y, m.y - bmin.y), 0.0f);
+    const float dz = fmaxf(fmaxf(bmax.z - m.z, m.z - bmin.z), 0.0f);
     return (dx * dx + dy * dy) + dz * dz;
 }
 
@@ -185,7 +201,7 @@ template <int PREC> constexpr int chunk_of() { return PREC == 2 ? 8 : 16; }
 // Slot of a lane's reduced value for chunk c in the per-group result array
 // (256 floats: 4 chunks x 64 values, or 8 chunks x 32 values).
 template <int PREC> __device__ __forceinline__ unsigned res_slot(unsigned c, unsigned ln) {
-    return PREC == 2 ? c * 32u + (ln >> 1) : c * 64u + ln;
+    return chunk_of<PREC>() == 8 ? c * 32u + (ln >> 1) : c * 64u + ln;
 }
 constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
 
@@ -464,13 +480,24 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             npc += na;
             tot_pc += na;
 
+            // One prefix sum gives the list offsets of both the opened leaves'
+            // particles (low half; leaves of 32 or more particles count 0 here
+            // and go by rounds below) and the opened internal cells' children
+            // (high half): sums stay below 64 * 32 and 64 * 8.
+            unsigned rem = leaf ? t.y : 0u, src = t.x;
+            const unsigned nc = push ? nch : 0u;
+            const bool big = __ballot(rem > 31u) != 0;
+            const unsigned packed = (big ? 0u : rem) | (nc << 16);
+            const unsigned incl = wave_incl_scan(packed);
+            const unsigned excl = incl - packed;
+            const unsigned both = uniform(__builtin_amdgcn_readlane(incl, 63));
+
             // opened leaves -> particle-particle list: whole leaves in one round
             // when every leaf holds fewer than 32 particles and they fit after a
             // flush, else in rounds of at most per_round particles per lane
-            unsigned rem = leaf ? t.y : 0u, src = t.x;
-            if (__ballot(rem > 0) && !__ballot(rem > 31u)) {
-                unsigned sum;
-                const unsigned off = small_excl_scan<5>(rem, &sum);
+            if (!big && (both & 0xffffu)) {
+                const unsigned sum = both & 0xffffu;
+                const unsigned off = excl & 0xffffu;
                 if (sum + 63u <= a.pp_cap) {
                     if (npp + sum > a.pp_cap)
                         npp = flush_list<PREC, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
@@ -494,9 +521,8 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             }
 
             // opened internal cells -> children onto the stack
-            unsigned nsum;
-            const unsigned nc = push ? nch : 0u;
-            const unsigned off = small_excl_scan(nc, &nsum);
+            const unsigned nsum = both >> 16;
+            const unsigned off = excl >> 16;
             const unsigned used = st - sb;
             if (used + nsum > WALK_LSTACK) {  // spill the bottom of the LDS ring
                 const unsigned need = used + nsum - WALK_LSTACK;
@@ -525,13 +551,13 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
 
         // results back to the caller's order
         constexpr int CHUNK = chunk_of<PREC>();
-        constexpr bool TERM = PREC == 2;
+        constexpr bool HALF = CHUNK == 8;
         // value held by this lane: bitrev6(ln) (64 per chunk) or its low five
         // bits (32 per chunk, lanes ln and ln ^ 1 alike: the even one stores)
-        const unsigned idx = TERM ? (bitrev6(ln) & 31u) : bitrev6(ln);
+        const unsigned idx = HALF ? (bitrev6(ln) & 31u) : bitrev6(ln);
         const unsigned comp = idx & 3u;
         for (unsigned c = 0; c * CHUNK < ge; c++) {
-            const unsigned pi = c * CHUNK + (idx >> 2) + ((TERM && (ln & 1u)) ? 64u : 0u);
+            const unsigned pi = c * CHUNK + (idx >> 2) + ((HALF && (ln & 1u)) ? 64u : 0u);
             if (pi < ge) {
                 const unsigned slot = res_slot<PREC>(c, ln);
                 float val = s_res[slot];

@@ -355,6 +355,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
     __shared__ float s_res[256];
     __shared__ float s_cmp[PREC ? 256 : 64];
     __shared__ uint32_t s_idx[64];  // group particle evaluated in each lane
+    __shared__ uint32_t s_perm[64];  // caller's index of each group particle
     const unsigned ln = lane64();
     uint32_t *gstk = a.wstack + (size_t)blockIdx.x * STACK_CAP;
     if (a.hdr->flags & (FLAG_NONFINITE | FLAG_NEGMASS | FLAG_CELLCAP)) return;
@@ -374,10 +375,15 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
         if (slot >= ngroups) break;
         const unsigned g = a.order ? uniform(a.order[slot]) : slot;
         const uint2 gr = a.groups[g];
+        // the anchor's record (its lists' place in the pool) is read now, so that
+        // it arrives while the group's box is formed
+        const uint4 rec = SHARED ? a.arec[uniform(a.anchor[g])] : make_uint4(0u, 0u, 0u, 0u);
         const unsigned gf = uniform(gr.x), gn = uniform(gr.y & 255u), glev = uniform((gr.y >> 8) & 255u);
         const unsigned root = uniform(gr.y >> 16);  // level-0 cells are the systems' roots, in system order
         const unsigned gl = min(ln, gn - 1);
         const float4 p0 = a.spos[gf + gl];
+        // each lane's particle in the caller's order, kept in LDS for the results
+        const unsigned pm = a.perm[gf + gl];
         float3 bmin = make_float3(p0.x, p0.y, p0.z), bmax = bmin;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -391,10 +397,11 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
         // The particles evaluated: all of the group's, or only its active ones
         // (an active walk), packed into the first `ge` lanes.  The interaction
         // lists are the whole group's either way (its box above).
-        const bool due = ln < gn && (!a.active || a.active[a.perm[gf + gl]] != 0);
+        const bool due = ln < gn && (!a.active || a.active[pm] != 0);
         const unsigned long long dm = __ballot(due);
         const unsigned ge = (unsigned)__popcll(dm);
         if (due) s_idx[rank_below(dm)] = ln;
+        s_perm[ln] = pm;
         __syncthreads();
         const unsigned pv = s_idx[ln];
         const unsigned pj = ln < ge ? pv : 0u;
@@ -420,7 +427,6 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             // stack starts with the cells left (sorted by level, shallowest at the
             // bottom, so that stack levels never decrease towards the top), in the
             // LDS ring, which is empty here and holds all of them (<= PREFIX_S_CAP)
-            const uint4 rec = a.arec[uniform(a.anchor[g])];
             seeded = uniform(rec.w) == 1u;
             if (seeded) {
                 const unsigned off = uniform(rec.x), nf = uniform(rec.y), ns = uniform(rec.z);
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
                 float val = s_res[slot];
                 if (PREC) val = val - s_cmp[slot];
                 val *= a.G;
-                const size_t orig = a.perm[gf + s_idx[pi]];
+                const size_t orig = s_perm[s_idx[pi]];
                 if (comp < 3) a.acc[3 * orig + comp] = val;
                 else a.pot[orig] = val;
             }

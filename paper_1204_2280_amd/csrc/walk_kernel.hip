@@ -472,7 +472,12 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             const float4 mc = a.cmac[c];
             const unsigned lvl = (t.w >> 8) & 255u, nch = t.w & 255u;
             const bool anc = t.x <= gf && gf < t.x + t.y && lvl <= glev;
-            const bool accept = valid && !anc && mac_accept(bmin, bmax, mc);
+            // The opening test is taken in every lane and combined without
+            // short-circuit: were it skipped for ancestors, the compiler would
+            // issue the cell's MAC load only after its topology had arrived,
+            // two dependent round trips per step instead of one.
+            const bool far = mac_accept(bmin, bmax, mc);
+            const bool accept = valid & !anc & far;
             const bool opened = valid && !accept;
             const bool leaf = opened && nch == 0;
             const bool push = opened && nch != 0;
@@ -691,8 +696,12 @@ __device__ bool anchor_lists(const WalkArgs &a, unsigned A, uint32_t *s_stk, uin
             const bool valid = k * 64u + ln < m;
             const unsigned lvl = (t[k].w >> 8) & 255u, nch = t[k].w & 255u;
             const bool anc = t[k].x <= af && af < t[k].x + t[k].y && lvl <= alev;
-            const bool open = valid && (anc || !(far_d2(bmin, bmax, mc[k]) > mc[k].w));
-            const bool accept = valid && !open && mac_accept(bmin, bmax, mc[k]);
+            // both tests in every lane, no short-circuit: the MAC loads then go
+            // out with the topology loads (see the group walk)
+            const bool reach = !(far_d2(bmin, bmax, mc[k]) > mc[k].w);
+            const bool far = mac_accept(bmin, bmax, mc[k]);
+            const bool open = valid & (anc | reach);
+            const bool accept = valid & !open & far;
             const bool left = valid && !accept && (!open || nch == 0);
             const unsigned long long am = __ballot(accept);
             const unsigned na = (unsigned)__popcll(am);

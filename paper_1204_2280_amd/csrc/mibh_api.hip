@@ -125,7 +125,7 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.hist = (uint32_t *)take(4 * RADIX * ntiles);
     t.btot = (uint32_t *)take(4 * RADIX);
     t.ppack = (float4 *)take(16 * n);
-    t.spos = (float4 *)take(16 * n);
+    t.spos = (float4 *)take(16 * (n + 1));  // + the padding particle
     t.cl = (int8_t *)take(n);
     t.lvinfo = (uchar4 *)take(4 * n);
     t.blkcnt = (uint32_t *)take(4 * NCOUNTERS * nblk);
@@ -135,8 +135,8 @@ size_t layout(int64_t n_max, const mibh_params &p, char *base, Buffers *b) {
     t.delta = (double *)take(8 * cap_cells);
     t.cbox = (float *)take(24 * cap_cells);
     t.lside = (double *)take(8 * cap_cells);
-    t.cmac = (float4 *)take(16 * cap_cells);
-    t.ceval = (float4 *)take(32 * cap_cells);
+    t.cmac = (float4 *)take(16 * (cap_cells + 1));   // + the padding cell
+    t.ceval = (float4 *)take(32 * (cap_cells + 1));
     t.groups = (uint2 *)take(8 * n);
     t.gcounts = (uint2 *)take(8 * n);
     t.wstack = (uint32_t *)take(4 * (size_t)STACK_CAP * waves);

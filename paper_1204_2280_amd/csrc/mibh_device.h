@@ -137,6 +137,11 @@ constexpr unsigned PREFIX_STEP = 4;     // stack cells per lane in one step of a
 constexpr unsigned PREFIX_RING = 4096;  // LDS stack ring of the anchor-list pass
 constexpr unsigned WALK_PC_LDS = 1024;  // particle-cell list
 constexpr unsigned WALK_PP_LDS = 512;   // particle-particle list
+static_assert(WALK_PC_LDS % 64 == 0 && WALK_PP_LDS % 64 == 0, "lists hold whole 64-entry tiles");
+// A list's last tile is padded with a massless source this far away (its
+// terms are exact zeros): the cell at index cap_cells (cmac, ceval) and the
+// particle at index n_max (spos), one entry past the cells and particles.
+constexpr float WALK_FAR = 1.0e18f;
 
 // Device pointers carved from the caller's workspace.
 struct Buffers {

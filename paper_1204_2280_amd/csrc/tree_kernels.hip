@@ -232,8 +232,15 @@ __global__ __launch_bounds__(256) void k_bbox_final(const float *__restrict__ pa
 // Header reset, before the per-system reductions of one build.  The flags of
 // the previous build move into the sticky word, so that a driver running many
 // steps still sees a condition that one of its earlier builds met.
-__global__ void k_header_reset(unsigned n, unsigned nsys, Header *__restrict__ hdr) {
+__global__ void k_header_reset(unsigned n, unsigned nsys, Header *__restrict__ hdr, float4 *__restrict__ cmac,
+                               float4 *__restrict__ ceval, float4 *__restrict__ spos, unsigned cap_cells,
+                               unsigned n_max) {
     if (threadIdx.x == 0) {
+        // the walk's padding cell and particle: massless, far away
+        cmac[cap_cells] = make_float4(WALK_FAR, WALK_FAR, WALK_FAR, 0.0f);
+        ceval[2 * (size_t)cap_cells] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        ceval[2 * (size_t)cap_cells + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        spos[n_max] = make_float4(WALK_FAR, WALK_FAR, WALK_FAR, 0.0f);
         hdr->nsys = nsys;
         hdr->sticky |= hdr->flags;
         hdr->flags = 0;
@@ -248,7 +255,8 @@ __global__ void k_header_reset(unsigned n, unsigned nsys, Header *__restrict__ h
 hipError_t launch_bbox(const Buffers &b, const float *pos, const float *mass, unsigned n, unsigned nsys,
                        hipStream_t s) {
     const unsigned per = max((unsigned)BBOX_MIN_BLOCKS, (unsigned)BBOX_BLOCKS / nsys);
-    hipLaunchKernelGGL(k_header_reset, dim3(1), dim3(64), 0, s, n, nsys, b.hdr);
+    hipLaunchKernelGGL(k_header_reset, dim3(1), dim3(64), 0, s, n, nsys, b.hdr, b.cmac, b.ceval, b.spos, b.cap_cells,
+                       b.n_max);
     hipLaunchKernelGGL(k_bbox_partial, dim3(per, nsys), dim3(256), 0, s, pos, mass, b.sys_off, b.bbox_part);
     hipLaunchKernelGGL(k_bbox_final, dim3(nsys), dim3(256), 0, s, b.bbox_part, per, n, nsys, b.hdr, b.cube);
     return hipGetLastError();

@@ -177,6 +177,7 @@ struct WalkArgs {
     float *acc, *pot;
     float eps2, G;
     unsigned pc_cap, pp_cap;
+    unsigned dcell, dpart;   // padding cell and particle (massless, far)
     // shared-prefix walk
     const float *cbox;       // cells' particle boxes
     const uint32_t *anchor;  // anchor cell of each group
@@ -203,11 +204,11 @@ template <int PREC> constexpr int chunk_of() { return PREC == 2 ? 8 : 16; }
 template <int PREC> __device__ __forceinline__ unsigned res_slot(unsigned c, unsigned ln) {
     return chunk_of<PREC>() == 8 ? c * 32u + (ln >> 1) : c * 64u + ln;
 }
-constexpr float FAR = 1.0e18f;   // position of padding sources (massless, far)
-
-// Evaluates `npcl` particle-cell entries and `nppl` particle-particle entries
-// for all `gn` group particles and adds the results into s_res (one value per
-// lane per chunk): one reduction per chunk covers both lists.
+// Evaluates `npcl` particle-cell entries and `nppl` particle-particle entries,
+// both whole 64-entry tiles (a list's last tile is padded with the massless far
+// cell or particle), for all `gn` group particles and adds the results into
+// s_res (one value per lane per chunk): one reduction per chunk covers both
+// lists.  Whole tiles need no per-lane test or substitute in the tile loops.
 template <int PREC>
 __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, const uint32_t *ppl, unsigned nppl,
                          unsigned gn, float px, float py, float pz, float *s_res, float *s_cmp) {
@@ -237,15 +238,8 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
             // read back in every tile.
             unsigned cn_t = cn;
             asm volatile("" : "+s"(cn_t));
-            const unsigned k = t0 + ln;
-            const bool valid = k < npcl;
-            const unsigned e = valid ? pcl[k] : 0u;
-            float4 m = a.cmac[e], q0 = a.ceval[2 * (size_t)e], q1 = a.ceval[2 * (size_t)e + 1];
-            if (!valid) {
-                m = make_float4(FAR, FAR, FAR, 0.0f);
-                q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                q1 = q0;
-            }
+            const unsigned e = pcl[t0 + ln];
+            const float4 m = a.cmac[e], q0 = a.ceval[2 * (size_t)e], q1 = a.ceval[2 * (size_t)e + 1];
 #pragma unroll
             for (int ii = 0; ii < CHUNK; ii++) {
                 if ((unsigned)ii < cn_t) {
@@ -280,18 +274,9 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
             }
         }
         for (unsigned t0 = 0; t0 < nppl; t0 += 64) {
-            // The particle count of the chunk is taken as new in every tile, so
-            // that its 16 comparisons are made in place (scalar compares) instead
-            // of being kept as 16 lane masks across the loop: 32 scalar registers
-            // more than the wave can hold, spilled to vector-register lanes and
-            // read back in every tile.
-            unsigned cn_t = cn;
+            unsigned cn_t = cn;  // in place in every tile, as above
             asm volatile("" : "+s"(cn_t));
-            const unsigned k = t0 + ln;
-            const bool valid = k < nppl;
-            const unsigned e = valid ? ppl[k] : 0u;
-            float4 s = a.spos[e];
-            if (!valid) s = make_float4(FAR, FAR, FAR, 0.0f);
+            const float4 s = a.spos[ppl[t0 + ln]];
 #pragma unroll
             for (int ii = 0; ii < CHUNK; ii++) {
                 if ((unsigned)ii < cn_t) {
@@ -319,12 +304,12 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
     }
 }
 
-// Evaluates the list's whole 64-entry tiles (all entries if `all`), moves the
-// remaining entries to the front and returns their number.
+// Evaluates the list's whole 64-entry tiles, moves the remaining entries to
+// the front and returns their number.
 template <int PREC, bool PC>
-__device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, bool all, unsigned gn, float px,
-                               float py, float pz, float *s_res, float *s_cmp) {
-    const unsigned ne = all ? n : (n & ~63u);
+__device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, unsigned gn, float px, float py,
+                               float pz, float *s_res, float *s_cmp) {
+    const unsigned ne = n & ~63u;
     __syncthreads();  // list entries written by other lanes are visible
     if (ne) {
         if (PC) evaluate<PREC>(a, list, ne, list, 0u, gn, px, py, pz, s_res, s_cmp);
@@ -435,7 +420,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
                 for (unsigned k0 = 0; k0 < nf; k0 += 64) {
                     const unsigned cnt = min(64u, nf - k0);
                     if (npc + cnt > pc_cap)
-                        npc = flush_list<PREC, true>(a, s_pc, npc, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                        npc = flush_list<PREC, true>(a, s_pc, npc, ge, p.x, p.y, p.z, s_res, s_cmp);
                     const unsigned v = ln < cnt ? a.pool[off + k0 + ln] : 0u;
                     if (ln < cnt) s_pc[npc + ln] = v;
                     npc += cnt;
@@ -486,7 +471,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             const unsigned long long am = __ballot(accept);
             const unsigned na = (unsigned)__popcll(am);
             if (npc + na > pc_cap)
-                npc = flush_list<PREC, true>(a, s_pc, npc, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                npc = flush_list<PREC, true>(a, s_pc, npc, ge, p.x, p.y, p.z, s_res, s_cmp);
             if (accept) s_pc[npc + rank_below(am)] = c;
             npc += na;
             tot_pc += na;
@@ -511,7 +496,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
                 const unsigned off = excl & 0xffffu;
                 if (sum + 63u <= a.pp_cap) {
                     if (npp + sum > a.pp_cap)
-                        npp = flush_list<PREC, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                        npp = flush_list<PREC, false>(a, s_pp, npp, ge, p.x, p.y, p.z, s_res, s_cmp);
                     for (unsigned j = 0; j < rem; j++) s_pp[npp + off + j] = src + j;
                     npp += sum;
                     tot_pp += sum;
@@ -523,7 +508,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
                 unsigned sum;
                 const unsigned off = small_excl_scan(take, &sum);
                 if (npp + sum > a.pp_cap)
-                    npp = flush_list<PREC, false>(a, s_pp, npp, false, ge, p.x, p.y, p.z, s_res, s_cmp);
+                    npp = flush_list<PREC, false>(a, s_pp, npp, ge, p.x, p.y, p.z, s_res, s_cmp);
                 for (unsigned j = 0; j < take; j++) s_pp[npp + off + j] = src + j;
                 npp += sum;
                 tot_pp += sum;
@@ -556,8 +541,14 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             continue;
         }
         if (npc + npp) {
+            // both lists' last tiles padded with the massless far cell and
+            // particle (npc <= pc_cap and npp <= pp_cap, so the padded lists
+            // stay within their LDS arrays, whole tiles long)
+            const unsigned npc_t = (npc + 63u) & ~63u, npp_t = (npp + 63u) & ~63u;
+            if (npc + ln < npc_t) s_pc[npc + ln] = a.dcell;
+            if (npp + ln < npp_t) s_pp[npp + ln] = a.dpart;
             __syncthreads();  // list entries written by other lanes are visible
-            evaluate<PREC>(a, s_pc, npc, s_pp, npp, ge, p.x, p.y, p.z, s_res, s_cmp);
+            evaluate<PREC>(a, s_pc, npc_t, s_pp, npp_t, ge, p.x, p.y, p.z, s_res, s_cmp);
         }
 
         // results back to the caller's order
@@ -836,6 +827,8 @@ hipError_t launch_walk(const Buffers &b, unsigned n, unsigned nsys, float eps2, 
     a.G = G;
     a.pc_cap = b.pc_cap;
     a.pp_cap = b.pp_cap;
+    a.dcell = b.cap_cells;
+    a.dpart = b.n_max;
     a.cbox = b.cbox;
     a.anchor = b.anchor;
     a.arec = b.arec;

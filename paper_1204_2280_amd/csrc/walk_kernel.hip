@@ -210,8 +210,9 @@ template <int PREC> __device__ __forceinline__ unsigned res_slot(unsigned c, uns
 // s_res (one value per lane per chunk): one reduction per chunk covers both
 // lists.  Whole tiles need no per-lane test or substitute in the tile loops.
 template <int PREC>
-__device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, const uint32_t *ppl, unsigned nppl,
-                         unsigned gn, float px, float py, float pz, float *s_res, float *s_cmp) {
+__device__ void evaluate(const WalkArgs &a, const uint32_t *fl, unsigned nfl, const uint32_t *pcl, unsigned npcl,
+                         const uint32_t *ppl, unsigned nppl, unsigned gn, float px, float py, float pz, float *s_res,
+                         float *s_cmp) {
     constexpr int CHUNK = chunk_of<PREC>();
     constexpr int NV = 4 * CHUNK;
     constexpr bool TERM = PREC == 2;
@@ -230,7 +231,13 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
         float v[NV], cv[NV];
 #pragma unroll
         for (int j = 0; j < NV; j++) { v[j] = 0.0f; cv[j] = 0.0f; }
-        for (unsigned t0 = 0; t0 < npcl; t0 += 64) {
+        // particle-cell tiles: the shared list in the pool (fl), then the
+        // group's own list in LDS (pcl), one loop over both
+        const uint32_t *lst = fl;
+        unsigned nl = nfl;
+#pragma unroll 1
+        for (int seg = 0; seg < 2; seg++, lst = pcl, nl = npcl)
+        for (unsigned t0 = 0; t0 < nl; t0 += 64) {
             // The particle count of the chunk is taken as new in every tile, so
             // that its 16 comparisons are made in place (scalar compares) instead
             // of being kept as 16 lane masks across the loop: 32 scalar registers
@@ -238,7 +245,7 @@ __device__ void evaluate(const WalkArgs &a, const uint32_t *pcl, unsigned npcl, 
             // read back in every tile.
             unsigned cn_t = cn;
             asm volatile("" : "+s"(cn_t));
-            const unsigned e = pcl[t0 + ln];
+            const unsigned e = lst[t0 + ln];
             const float4 m = a.cmac[e], q0 = a.ceval[2 * (size_t)e], q1 = a.ceval[2 * (size_t)e + 1];
 #pragma unroll
             for (int ii = 0; ii < CHUNK; ii++) {
@@ -312,8 +319,8 @@ __device__ unsigned flush_list(const WalkArgs &a, uint32_t *list, unsigned n, un
     const unsigned ne = n & ~63u;
     __syncthreads();  // list entries written by other lanes are visible
     if (ne) {
-        if (PC) evaluate<PREC>(a, list, ne, list, 0u, gn, px, py, pz, s_res, s_cmp);
-        else evaluate<PREC>(a, list, 0u, list, ne, gn, px, py, pz, s_res, s_cmp);
+        if (PC) evaluate<PREC>(a, nullptr, 0u, list, ne, list, 0u, gn, px, py, pz, s_res, s_cmp);
+        else evaluate<PREC>(a, nullptr, 0u, list, 0u, list, ne, gn, px, py, pz, s_res, s_cmp);
     }
     const unsigned r = n - ne;
     if (r) {
@@ -406,26 +413,23 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
         unsigned npc = 0, npp = 0, tot_pc = 0, tot_pp = 0;
         bool overflow = false;
         bool seeded = false;
+        unsigned f_off = 0, f_n = 0;  // the shared accepted cells, whole tiles in the pool
         if (SHARED) {
             // the lists shared by the groups below this group's anchor cell: its
-            // accepted cells go into the particle-cell list as they are, and the
-            // stack starts with the cells left (sorted by level, shallowest at the
-            // bottom, so that stack levels never decrease towards the top), in the
-            // LDS ring, which is empty here and holds all of them (<= PREFIX_S_CAP)
+            // accepted cells are evaluated in place, from the pool, with the
+            // group's own lists at its end, and the stack starts with the cells
+            // left (sorted by level, shallowest at the bottom, so that stack levels
+            // never decrease towards the top), in the LDS ring, which is empty here
+            // and holds all of them (<= PREFIX_S_CAP)
             seeded = uniform(rec.w) == 1u;
             if (seeded) {
                 const unsigned off = uniform(rec.x), nf = uniform(rec.y), ns = uniform(rec.z);
-                for (unsigned i = ln; i < ns; i += 64) s_stk[i] = a.pool[off + nf + i];
+                const unsigned nfp = (nf + 63u) & ~63u;
+                for (unsigned i = ln; i < ns; i += 64) s_stk[i] = a.pool[off + nfp + i];
                 st = ns;
-                for (unsigned k0 = 0; k0 < nf; k0 += 64) {
-                    const unsigned cnt = min(64u, nf - k0);
-                    if (npc + cnt > pc_cap)
-                        npc = flush_list<PREC, true>(a, s_pc, npc, ge, p.x, p.y, p.z, s_res, s_cmp);
-                    const unsigned v = ln < cnt ? a.pool[off + k0 + ln] : 0u;
-                    if (ln < cnt) s_pc[npc + ln] = v;
-                    npc += cnt;
-                    tot_pc += cnt;
-                }
+                f_off = off;
+                f_n = nfp;
+                tot_pc += nf;
             }
         }
         if (!seeded) {
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             atomicOr(&a.hdr->flags, FLAG_STACK);
             continue;
         }
-        if (npc + npp) {
+        if (f_n + npc + npp) {
             // both lists' last tiles padded with the massless far cell and
             // particle (npc <= pc_cap and npp <= pp_cap, so the padded lists
             // stay within their LDS arrays, whole tiles long)
@@ -548,7 +552,8 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
             if (npc + ln < npc_t) s_pc[npc + ln] = a.dcell;
             if (npp + ln < npp_t) s_pp[npp + ln] = a.dpart;
             __syncthreads();  // list entries written by other lanes are visible
-            evaluate<PREC>(a, s_pc, npc_t, s_pp, npp_t, ge, p.x, p.y, p.z, s_res, s_cmp);
+            evaluate<PREC>(a, f_n ? a.pool + f_off : nullptr, f_n, s_pc, npc_t, s_pp, npp_t, ge, p.x, p.y, p.z,
+                           s_res, s_cmp);
         }
 
         // results back to the caller's order
@@ -783,18 +788,21 @@ __global__ __launch_bounds__(64) void k_walk_prefix(WalkArgs a, unsigned *__rest
         bool ok = anchor_lists(a, A, s_stk, gstk, pf, &nf, &ns);
         nf = uniform(nf);
         ns = uniform(ns);
+        // F takes whole 64-entry tiles in the pool (padded with the massless far
+        // cell): the groups evaluate it in place
+        const unsigned nfp = (nf + 63u) & ~63u;
         unsigned long long off64 = 0;
         if (ok) {  // every lane calls the atomic (lane 0 adds), see queue_next
-            off64 = atomicAdd(pool_head, ln == 0 ? (unsigned long long)(nf + ns) : 0ull);
+            off64 = atomicAdd(pool_head, ln == 0 ? (unsigned long long)(nfp + ns) : 0ull);
             off64 = ((unsigned long long)uniform((unsigned)(off64 >> 32)) << 32) | uniform((unsigned)off64);
-            ok = off64 + nf + ns <= pool_cap;
+            ok = off64 + nfp + ns <= pool_cap;
         }
         if (!ok) atomicAdd(nfail, ln == 0 ? 1u : 0u);  // ok is wave-uniform
         const unsigned off = (unsigned)off64;  // < 2^32 when ok
         if (ok) {
-            for (unsigned i = ln; i < nf; i += 64) pool[off + i] = pf[i];
+            for (unsigned i = ln; i < nfp; i += 64) pool[off + i] = i < nf ? pf[i] : a.dcell;
             const uint32_t *pseed = pf + PREFIX_F_CAP + PREFIX_S_CAP;
-            for (unsigned i = ln; i < ns; i += 64) pool[off + nf + i] = pseed[i];
+            for (unsigned i = ln; i < ns; i += 64) pool[off + nfp + i] = pseed[i];
         }
         // every lane stores the same record: no lane-dependent branch in this loop
         arec[A] = ok ? make_uint4(off, nf, ns, 1u) : make_uint4(0u, 0u, 0u, 0u);

@@ -593,9 +593,10 @@ __global__ __launch_bounds__(64, 4) void k_walk(WalkArgs a) {
 //     either contain A, and ancestors of A are opened, or lie inside A, with
 //     its centre of mass inside A's box at distance 0);
 //   * any other cell is left to each group.
-// Each group then starts with the accepted cells (F) in its particle-cell list
-// and the cells left (S) on its stack and walks on as usual: the same cells
-// are accepted and opened as in a walk from the root, in another order.
+// Each group then starts with the cells left (S) on its stack and walks on as
+// usual, and evaluates the accepted cells (F, whole tiles in the pool) in place
+// with its own lists at its end: the same cells are accepted and opened as in
+// a walk from the root, and summed in another order.
 // --------------------------------------------------------------------------
 
 // Anchor of every group: the cell at level max(level - up, 0) that holds the

@@ -115,10 +115,14 @@ def test_repeated_walks_and_determinism(ctx, orc):
     assert torch.equal(a1, a3) and torch.equal(p1, p3)
 
 
-def test_small_list_capacities_force_flushes(orc):
-    """Tiny per-wave list capacities exercise the mid-traversal evaluation flushes."""
+@pytest.mark.parametrize("pc_cap,pp_cap,n_max", [(128, 128, 6000), (200, 130, 5003), (1000, 511, 5003)])
+def test_small_list_capacities_force_flushes(orc, pc_cap, pp_cap, n_max):
+    """Small per-wave list capacities exercise the mid-traversal evaluation flushes; capacities
+    that are not whole 64-entry tiles exercise the padding of the lists' last tiles, and a
+    context of exactly n particles puts the padding particle right after the last one."""
     pos, mass = _case("plummer_5003")
-    c = gpu_context(6000, pc_cap=128, pp_cap=128, walk_waves=37)
+    print(f"[gpu] list capacities {pc_cap}/{pp_cap}, n_max {n_max}", flush=True)
+    c = gpu_context(n_max, pc_cap=pc_cap, pp_cap=pp_cap, walk_waves=37)
     g = run_gpu(c, pos, mass, 0.75, exports=("counts",))
     T = orc.Tree(pos, mass)
     T.walk(0.75)

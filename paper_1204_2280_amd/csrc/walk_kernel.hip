@@ -70,8 +70,9 @@ __device__ __forceinline__ unsigned small_excl_scan(unsigned v, unsigned *total)
 // values whose sums do not overflow: Hillis-Steele steps inside each row of 16
 // lanes (DPP row shifts 1, 2, 4, 8; a lane with no source lane adds 0), then the
 // row totals carried across rows by the GFX9 row broadcasts (lane 15 into rows 1
-// and 3, lane 31 into rows 2 and 3).  Six VALU instructions; the whole wave
-// must be active.
+// and 3, lane 31 into rows 2 and 3).  Six DPP steps (a move and an add each,
+// where the compiler does not fuse them) against two ballots and a shift-add
+// per bit for a ballot scan; the whole wave must be active.
 __device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
     v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
     v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
@@ -204,11 +205,13 @@ template <int PREC> constexpr int chunk_of() { return PREC == 2 ? 8 : 16; }
 template <int PREC> __device__ __forceinline__ unsigned res_slot(unsigned c, unsigned ln) {
     return chunk_of<PREC>() == 8 ? c * 32u + (ln >> 1) : c * 64u + ln;
 }
-// Evaluates `npcl` particle-cell entries and `nppl` particle-particle entries,
-// both whole 64-entry tiles (a list's last tile is padded with the massless far
-// cell or particle), for all `gn` group particles and adds the results into
-// s_res (one value per lane per chunk): one reduction per chunk covers both
-// lists.  Whole tiles need no per-lane test or substitute in the tile loops.
+// Evaluates the particle-cell entries `fl` (`nfl`, an anchor's shared cells in
+// the pool, or none) and `pcl` (`npcl`, in LDS) and the particle-particle
+// entries `ppl` (`nppl`), all whole 64-entry tiles (a list's last tile is padded
+// with the massless far cell or particle), for all `gn` group particles and
+// adds the results into s_res (one value per lane per chunk): one reduction per
+// chunk covers all the lists.  Whole tiles need no per-lane test or substitute
+// in the tile loops.
 template <int PREC>
 __device__ void evaluate(const WalkArgs &a, const uint32_t *fl, unsigned nfl, const uint32_t *pcl, unsigned npcl,
                          const uint32_t *ppl, unsigned nppl, unsigned gn, float px, float py, float pz, float *s_res,

@@ -410,7 +410,7 @@ def bench_variant_queue_order(w16, theta, steps, rounds=5):
             for _ in range(steps):
                 fn()
             got = ctx.profile_read()
-            if r > 0:  # round 0 warms every mode up
+            if r > 0:  # the first alternation warms every mode up
                 rec[mode].extend(got)
     out = {}
     for mode, rows in rec.items():
